@@ -1,0 +1,262 @@
+"""FP64 CPU oracle for linked ray tracing (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark import
+this package.  The arithmetic lives in ``oracle_rt.c`` (plain C, FP64), which is
+built with gcc into ``liboracle_rt.so`` next to it; this module only marshals
+numpy arrays.  It shares no code with the HIP path.
+
+Media are described by a dict:
+  {"kind": "grid", "c": float64[ny, nx], "h": h}
+  {"kind": "fisheye", "nx": nx, "ny": ny, "h": h, "c0": c0, "R": R}   (analytic)
+  {"kind": "linear", "nx": nx, "ny": ny, "h": h, "c0": c0, "ax": ax, "ay": ay}
+"""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle_rt.c")
+_LIB = os.path.join(_HERE, "liboracle_rt.so")
+
+LINKED, NOT_CONVERGED, NO_HIT, BAD_INPUT = 0, 1, 2, 3
+WARM, FIXED = 1, 2
+HEUN, RK4 = 2, 4
+LENGTH, DTDC = 0, 1
+
+
+def build(force=True, src=_SRC, out=_LIB):
+    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
+        return out
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_bp = C.POINTER(C.c_int8)
+
+
+def lib():
+    if _lib is None:
+        build(force=False)
+        _load(_LIB)
+    return _lib
+
+
+def _load(path):
+    global _lib
+    L = C.CDLL(path)
+    med = [C.c_int, C.c_int, C.c_int, C.c_double, _dp, _dp]
+    L.or_gradient.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
+    L.or_trace.argtypes = med + [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
+                                 C.c_int, C.c_int, C.c_int, C.c_int, _ip, _dp, _dp, _dp, _dp, _ip, _bp]
+    L.or_march_points.argtypes = med + [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int,
+                                        C.c_int, C.c_int, C.c_double, _dp, C.c_int, _dp, _dp]
+    L.or_march_free.argtypes = med + [C.c_int, C.c_double, _dp, _dp, C.c_int, _dp]
+    L.or_interp.argtypes = med + [C.c_int, _dp, _dp, _dp, _dp]
+    L.or_weights_row.argtypes = [C.c_int, C.c_int, C.c_double, _dp, C.c_int, C.c_double, C.c_double,
+                                 C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double, _ip, _dp,
+                                 C.c_long]
+    L.or_weights_row.restype = C.c_long
+    L.or_adjoint.argtypes = [C.c_int, C.c_int, C.c_double, _dp, C.c_int, C.c_double, C.c_double, C.c_int,
+                             C.c_double, C.c_int, C.c_int, _ip, _dp, _bp, _dp, C.c_int, _dp]
+    L.or_rayborn_rho.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
+    _lib = L
+
+
+class use_library:
+    """Context manager that swaps in another build of the oracle (used by the
+    test that plants mistakes in a copy of the oracle source)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = lib()
+        _lib = None
+        _load(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+def _b(a):
+    return a.ctypes.data_as(_bp)
+
+
+def _medium_args(medium):
+    kind = medium["kind"]
+    h = float(medium["h"])
+    if kind == "grid":
+        c = np.ascontiguousarray(medium["c"], dtype=np.float64)
+        ny, nx = c.shape
+        return [0, nx, ny, h, _d(c), None], (c,)
+    par = np.zeros(4)
+    if kind == "fisheye":
+        par[:2] = (medium["c0"], medium["R"])
+        code = 1
+    elif kind == "linear":
+        par[:3] = (medium["c0"], medium["ax"], medium["ay"])
+        code = 2
+    else:
+        raise ValueError(kind)
+    return [code, int(medium.get("nx", 8)), int(medium.get("ny", 8)), h, None, _d(par)], (par,)
+
+
+def grid_medium(c, h):
+    return {"kind": "grid", "c": np.asarray(c, dtype=np.float64), "h": float(h)}
+
+
+def gradient(c):
+    """Per-index second-order differences of c [ny, nx] -> (gx, gy)."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    ny, nx = c.shape
+    gx = np.empty_like(c)
+    gy = np.empty_like(c)
+    if lib().or_gradient(nx, ny, _d(c), _d(gx), _d(gy)):
+        raise ValueError("grid too small")
+    return gx, gy
+
+
+def interp(medium, pts):
+    """c and per-pixel gradient at pixel points pts [n, 2] (ring-centred)."""
+    args, keep = _medium_args(medium)
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    n = pts.shape[0]
+    cv, gx, gy = np.empty(n), np.empty(n), np.empty(n)
+    if lib().or_interp(*args, n, _d(pts), _d(cv), _d(gx), _d(gy)):
+        raise ValueError("bad medium")
+    return cv, gx, gy
+
+
+def _integ_code(integ):
+    return {"heun": HEUN, "rk4": RK4, HEUN: HEUN, RK4: RK4}[integ]
+
+
+def trace(medium, ring, pairs, theta=None, integ="rk4", ds_px=0.25, tol_px=1e-3, max_marches=30,
+          max_steps=0, fixed=False, warm=False):
+    """Linked (or fixed-angle) tracing of pairs [n, 2] = (emitter, receiver).
+
+    ring = (n_elem, radius_m, phi0).  Returns a dict of numpy arrays:
+    theta, tof (s), len (m), miss_px, n_marches, status."""
+    args, keep = _medium_args(medium)
+    n_elem, radius, phi0 = ring
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    n = pairs.shape[0]
+    th = np.zeros(n) if theta is None else np.array(theta, dtype=np.float64).copy()
+    T, L, miss = np.empty(n), np.empty(n), np.empty(n)
+    nm = np.empty(n, dtype=np.int32)
+    st = np.empty(n, dtype=np.int8)
+    flags = (FIXED if fixed else 0) | (WARM if warm else 0)
+    rc = lib().or_trace(*args, int(n_elem), float(radius), float(phi0), _integ_code(integ), float(ds_px),
+                        float(tol_px), int(max_marches), int(max_steps), flags, n, _i(pairs), _d(th), _d(T),
+                        _d(L), _d(miss), _i(nm), _b(st))
+    if rc:
+        raise ValueError("bad arguments")
+    return {"theta": th, "tof": T, "len": L, "miss_px": miss, "n_marches": nm, "status": st}
+
+
+def march_points(medium, ring, e, r, theta, integ="rk4", ds_px=0.25, max_steps=0, cap=1 << 16):
+    """Samples of one fixed-angle march: (points [M+1, 2] px, ds', misfit g)."""
+    args, keep = _medium_args(medium)
+    n_elem, radius, phi0 = ring
+    pts = np.empty((cap, 2))
+    dsp, g = C.c_double(0), C.c_double(0)
+    n = lib().or_march_points(*args, int(n_elem), float(radius), float(phi0), _integ_code(integ), float(ds_px),
+                              int(max_steps), int(e), int(r), float(theta), _d(pts), cap, C.byref(dsp),
+                              C.byref(g))
+    if n < 0:
+        return None, float("nan"), float("nan")
+    return pts[: min(n, cap)].copy(), dsp.value, g.value
+
+
+def march_free(medium, x0_px, d0, n_steps, integ="rk4", ds_px=0.25):
+    """n_steps steps from x0 (pixels) along d0 without a ring: points [n+1, 2]."""
+    args, keep = _medium_args(medium)
+    x0 = np.ascontiguousarray(x0_px, dtype=np.float64)
+    d0 = np.ascontiguousarray(d0, dtype=np.float64)
+    pts = np.empty((n_steps + 1, 2))
+    if lib().or_march_free(*args, _integ_code(integ), float(ds_px), _d(x0), _d(d0), int(n_steps), _d(pts)):
+        raise ValueError("bad medium")
+    return pts
+
+
+def weights_row(c, h, ring, e, r, theta, integ="rk4", ds_px=0.25, max_steps=0):
+    """One system-matrix row (cols int32 sorted, vals float64 metres)."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    ny, nx = c.shape
+    n_elem, radius, phi0 = ring
+    cap = 1 << 15
+    while True:
+        cols = np.empty(cap, dtype=np.int32)
+        vals = np.empty(cap)
+        nnz = lib().or_weights_row(nx, ny, float(h), _d(c), int(n_elem), float(radius), float(phi0),
+                                   _integ_code(integ), float(ds_px), int(max_steps), int(e), int(r),
+                                   float(theta), _i(cols), _d(vals), cap)
+        if nnz < 0:
+            return None, None
+        if nnz <= cap:
+            return cols[:nnz].copy(), vals[:nnz].copy()
+        cap = int(nnz)
+
+
+def weights_csr(c, h, ring, pairs, theta, **kw):
+    """Whole system matrix as (rowptr int64, cols int32, vals float64)."""
+    rows = [weights_row(c, h, ring, int(e), int(r), float(t), **kw) for (e, r), t in zip(pairs, theta)]
+    counts = [0 if cc is None else len(cc) for cc, _ in rows]
+    rowptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    rowptr[1:] = np.cumsum(counts)
+    cols = np.concatenate([cc for cc, _ in rows if cc is not None] or [np.empty(0, np.int32)])
+    vals = np.concatenate([v for cc, v in rows if cc is not None] or [np.empty(0)])
+    return rowptr, cols, vals
+
+
+def adjoint(c, h, ring, pairs, theta, rho, weight="length", status=None, integ="rk4", ds_px=0.25,
+            max_steps=0):
+    """grad [ny, nx] = sum_i rho_i sum_m w_m h kappa_m phi_j(p_m)."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    ny, nx = c.shape
+    n_elem, radius, phi0 = ring
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    st = None if status is None else np.ascontiguousarray(status, dtype=np.int8)
+    grad = np.zeros((ny, nx))
+    mode = {"length": LENGTH, "dtdc": DTDC}[weight]
+    rc = lib().or_adjoint(nx, ny, float(h), _d(c), int(n_elem), float(radius), float(phi0), _integ_code(integ),
+                          float(ds_px), int(max_steps), pairs.shape[0], _i(pairs), _d(theta),
+                          None if st is None else _b(st), _d(rho), mode, _d(grad))
+    if rc:
+        raise ValueError("bad arguments")
+    return grad
+
+
+def rayborn_rho(tof, freqs, resid):
+    """rho_i = sum_k w_k Im(exp(-i w_k T_i) r_ik), w_k = 2 pi f_k."""
+    tof = np.ascontiguousarray(tof, dtype=np.float64)
+    freqs = np.ascontiguousarray(freqs, dtype=np.float64)
+    r = np.ascontiguousarray(resid).astype(np.complex128)
+    n, nf = r.shape
+    ri = np.ascontiguousarray(r.view(np.float64).reshape(n, nf, 2))
+    rho = np.empty(n)
+    lib().or_rayborn_rho(n, nf, _d(tof), _d(freqs), _d(ri), _d(rho))
+    return rho

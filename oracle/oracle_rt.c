@@ -1,0 +1,766 @@
+/*
+ * oracle_rt.c -- plain, slow FP64 CPU oracle for two-point (shooting) ray tracing
+ * through a gridded sound-speed map, with ray linking, travel time, path length,
+ * sparse ray-to-grid weights and their adjoint.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls
+ * this file; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code, header, table or constant with the HIP path.
+ *
+ * What it follows (arXiv 2511.18511):
+ *   - Sec. 3.2 (ray tracing): shooting method, an initial-value problem per ray in
+ *     the position x and unit direction d, driven by the medium and its gradient.
+ *   - Sec. 3.3 (grid-to-ray interpolation): bilinear interpolation of the field
+ *     and of its gradient, the gradient being taken from values on grid nodes,
+ *     using only the vertices of the enclosing cell.
+ *   - Sec. 3.4 (ray linking): misfit = angular discrepancy between the ray's
+ *     interception with the boundary and the receiver; secant update of the launch
+ *     angle (default), regula-falsi style bracketing; straight-ray initial guess
+ *     for a homogeneous start, warm start from previous launch angles.
+ *   - Sec. 3.1 (linearisation): a system-matrix row holds the interpolation
+ *     coefficients of the sampled ray points, accumulated per grid node.
+ *   - Sec. 4.2, trapezoid rule for the accumulated length with a partial last
+ *     step ds' whose end point is replaced by the interception point.
+ *   - Appendix: travel time obeys grad T . grad T = 1/c^2, T = integral ds / c.
+ *
+ * Readings where the paper is silent (the same list is kept with the design
+ * notes): c itself is interpolated and T integrates 1/c; the node gradient is
+ * second-order central differences, second-order one-sided at the grid edges;
+ * the ray ODE is dx/ds = d, dd/ds = -(G - (G.d) d)/c in pixel units
+ * (G = per-pixel gradient of c), integrated by classic RK4 or Heun, with d
+ * renormalised after every step; the last step is cut at the ring by a
+ * segment/circle intersection; the same trapezoid weights serve T, L and the
+ * weights; the misfit is the emitter-relative unwrapped angle; the secant is
+ * safeguarded by a sign bracket and by angle limits (details at link_pair).
+ *
+ * Units: positions in pixels relative to the grid centre (= ring centre), grid
+ * node (ix, iy) at pixel (ix - (nx-1)/2, iy - (ny-1)/2); c in m/s; h in metres.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_GRID 0
+#define OR_FISHEYE 1 /* analytic c = c0 (1 + |x|^2 / R^2), params {c0, R} */
+#define OR_LINEAR 2  /* analytic c = c0 + ax x + ay y,   params {c0, ax, ay} */
+
+#define ST_LINKED 0
+#define ST_NOT_CONVERGED 1
+#define ST_NO_HIT 2
+#define ST_BAD_INPUT 3
+
+#define OPT_WARM 1
+#define OPT_FIXED 2
+
+static const double PI = 3.14159265358979323846;
+
+typedef struct {
+    int kind;
+    int nx, ny;
+    double h;
+    const double *c; /* [ny][nx] */
+    double *gx, *gy; /* per-pixel gradient of c on nodes */
+    double p[4];
+} Medium;
+
+typedef struct {
+    int n_elem;
+    double radius_px;
+    double phi0;
+} Ring;
+
+typedef struct {
+    int integ; /* 2 = Heun, 4 = RK4 */
+    double ds;  /* step, pixels */
+    double tol; /* linking tolerance on the miss, pixels */
+    int max_marches;
+    int max_steps;
+    int flags;
+} Opts;
+
+/* ---------------------------------------------------------------- gradient -- */
+/* Second-order finite differences in index units along x (axis of ix) and y.
+   Interior: (f[i+1] - f[i-1]) / 2.  Edges: (-3 f0 + 4 f1 - f2) / 2 and
+   (3 f[n-1] - 4 f[n-2] + f[n-3]) / 2.  Needs n >= 3 along both axes. */
+int or_gradient(int nx, int ny, const double *c, double *gx, double *gy)
+{
+    if (nx < 3 || ny < 3) return -1;
+    for (int iy = 0; iy < ny; iy++) {
+        for (int ix = 0; ix < nx; ix++) {
+            double d;
+            if (ix == 0)
+                d = (-3.0 * c[iy * nx + 0] + 4.0 * c[iy * nx + 1] - c[iy * nx + 2]) / 2.0;
+            else if (ix == nx - 1)
+                d = (3.0 * c[iy * nx + nx - 1] - 4.0 * c[iy * nx + nx - 2] + c[iy * nx + nx - 3]) / 2.0;
+            else
+                d = (c[iy * nx + ix + 1] - c[iy * nx + ix - 1]) / 2.0;
+            gx[iy * nx + ix] = d;
+        }
+    }
+    for (int iy = 0; iy < ny; iy++) {
+        for (int ix = 0; ix < nx; ix++) {
+            double d;
+            if (iy == 0)
+                d = (-3.0 * c[0 * nx + ix] + 4.0 * c[1 * nx + ix] - c[2 * nx + ix]) / 2.0;
+            else if (iy == ny - 1)
+                d = (3.0 * c[(ny - 1) * nx + ix] - 4.0 * c[(ny - 2) * nx + ix] + c[(ny - 3) * nx + ix]) / 2.0;
+            else
+                d = (c[(iy + 1) * nx + ix] - c[(iy - 1) * nx + ix]) / 2.0;
+            gy[iy * nx + ix] = d;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------- bilinear cell -- */
+/* Enclosing cell of pixel position (px, py): lower-left node (ix, iy) and local
+   coordinates (t, s) in [0,1].  The cell index is clamped to the grid and the
+   local coordinates to [0,1].  Returns 0 on a NaN position. */
+static int locate(const Medium *m, double px, double py, int *ix, int *iy, double *t, double *s)
+{
+    double u = px + 0.5 * (m->nx - 1);
+    double v = py + 0.5 * (m->ny - 1);
+    if (!(u == u) || !(v == v)) return 0;
+    double fu = floor(u), fv = floor(v);
+    if (fu < 0) fu = 0;
+    if (fu > m->nx - 2) fu = m->nx - 2;
+    if (fv < 0) fv = 0;
+    if (fv > m->ny - 2) fv = m->ny - 2;
+    double tt = u - fu, ss = v - fv;
+    if (tt < 0) tt = 0;
+    if (tt > 1) tt = 1;
+    if (ss < 0) ss = 0;
+    if (ss > 1) ss = 1;
+    *ix = (int)fu;
+    *iy = (int)fv;
+    *t = tt;
+    *s = ss;
+    return 1;
+}
+
+/* Bilinear hat weights of the four cell corners, order (ix,iy), (ix+1,iy),
+   (ix,iy+1), (ix+1,iy+1). */
+static void hat4(double t, double s, double w[4])
+{
+    w[0] = (1.0 - t) * (1.0 - s);
+    w[1] = t * (1.0 - s);
+    w[2] = (1.0 - t) * s;
+    w[3] = t * s;
+}
+
+/* c (m/s) and its per-pixel gradient at pixel position (px, py). */
+static void medium_eval(const Medium *m, double px, double py, double *c, double *gx, double *gy)
+{
+    if (m->kind == OR_FISHEYE) {
+        double x = px * m->h, y = py * m->h, c0 = m->p[0], R = m->p[1];
+        *c = c0 * (1.0 + (x * x + y * y) / (R * R));
+        *gx = c0 * 2.0 * x / (R * R) * m->h;
+        *gy = c0 * 2.0 * y / (R * R) * m->h;
+        return;
+    }
+    if (m->kind == OR_LINEAR) {
+        double x = px * m->h, y = py * m->h;
+        *c = m->p[0] + m->p[1] * x + m->p[2] * y;
+        *gx = m->p[1] * m->h;
+        *gy = m->p[2] * m->h;
+        return;
+    }
+    int ix, iy;
+    double t, s, w[4];
+    if (!locate(m, px, py, &ix, &iy, &t, &s)) {
+        *c = NAN;
+        *gx = NAN;
+        *gy = NAN;
+        return;
+    }
+    hat4(t, s, w);
+    int n0 = iy * m->nx + ix, n1 = n0 + 1, n2 = n0 + m->nx, n3 = n2 + 1;
+    *c = w[0] * m->c[n0] + w[1] * m->c[n1] + w[2] * m->c[n2] + w[3] * m->c[n3];
+    *gx = w[0] * m->gx[n0] + w[1] * m->gx[n1] + w[2] * m->gx[n2] + w[3] * m->gx[n3];
+    *gy = w[0] * m->gy[n0] + w[1] * m->gy[n1] + w[2] * m->gy[n2] + w[3] * m->gy[n3];
+}
+
+/* ---------------------------------------------------------------- ray ODE -- */
+/* State y = (x1, x2, d1, d2).  dx/ds = d; dd/ds = -(G - (G.d) d) / c. */
+static void rhs(const Medium *m, const double y[4], double k[4])
+{
+    double c, gx, gy;
+    medium_eval(m, y[0], y[1], &c, &gx, &gy);
+    double gd = gx * y[2] + gy * y[3];
+    k[0] = y[2];
+    k[1] = y[3];
+    k[2] = -(gx - gd * y[2]) / c;
+    k[3] = -(gy - gd * y[3]) / c;
+}
+
+/* One step of length ds; the direction is renormalised afterwards. */
+static void step(const Medium *m, int integ, double ds, const double y[4], double out[4])
+{
+    double k1[4], k2[4], k3[4], k4[4], tmp[4];
+    if (integ == 2) { /* Heun: explicit trapezoid RK2 */
+        rhs(m, y, k1);
+        for (int i = 0; i < 4; i++) tmp[i] = y[i] + ds * k1[i];
+        rhs(m, tmp, k2);
+        for (int i = 0; i < 4; i++) out[i] = y[i] + ds / 2.0 * (k1[i] + k2[i]);
+    } else { /* classic fourth-order Runge-Kutta */
+        rhs(m, y, k1);
+        for (int i = 0; i < 4; i++) tmp[i] = y[i] + ds / 2.0 * k1[i];
+        rhs(m, tmp, k2);
+        for (int i = 0; i < 4; i++) tmp[i] = y[i] + ds / 2.0 * k2[i];
+        rhs(m, tmp, k3);
+        for (int i = 0; i < 4; i++) tmp[i] = y[i] + ds * k3[i];
+        rhs(m, tmp, k4);
+        for (int i = 0; i < 4; i++) out[i] = y[i] + ds / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    }
+    double nrm = sqrt(out[2] * out[2] + out[3] * out[3]);
+    out[2] /= nrm;
+    out[3] /= nrm;
+}
+
+/* --------------------------------------------------------------- one march -- */
+typedef struct {
+    int status;   /* ST_LINKED here means "hit the ring" */
+    int M;        /* index of the last sample (the interception point) */
+    double dsp;   /* partial last step, pixels */
+    double qx, qy;
+    double *pts;  /* samples p_0..p_M, [M+1][2] pixels (owned, malloc) */
+} March;
+
+static double mod2pi(double a)
+{
+    double r = fmod(a, 2.0 * PI);
+    if (r < 0) r += 2.0 * PI;
+    return r;
+}
+
+/* Traces one ray from pixel point (ex, ey) with initial direction angle psi0
+   until it crosses the ring |x| = R.  Samples p_m are the accepted step points;
+   the crossing step m is cut at the larger root t in (0,1] of
+   |p_{m-1} + t (p_m - p_{m-1})|^2 = R^2, the interception q replaces p_m and
+   ds' = t ds.  More than max_steps steps without a crossing -> ST_NO_HIT.  A
+   non-positive or NaN sound speed at a sample -> ST_BAD_INPUT. */
+static void march(const Medium *m, const Ring *ring, const Opts *o, double ex, double ey, double psi0, March *r)
+{
+    int cap = 1024, n = 1;
+    double *pts = (double *)malloc(sizeof(double) * 2 * cap);
+    double y[4] = {ex, ey, cos(psi0), sin(psi0)}, yn[4];
+    double R = ring->radius_px;
+    pts[0] = ex;
+    pts[1] = ey;
+    r->status = ST_NO_HIT;
+    r->M = 0;
+    r->dsp = 0;
+    r->qx = r->qy = NAN;
+    for (int mstep = 1; mstep <= o->max_steps; mstep++) {
+        double c, gx, gy;
+        medium_eval(m, y[0], y[1], &c, &gx, &gy);
+        if (!(c > 0.0)) {
+            r->status = ST_BAD_INPUT;
+            break;
+        }
+        step(m, o->integ, o->ds, y, yn);
+        if (n + 1 > cap) {
+            cap *= 2;
+            pts = (double *)realloc(pts, sizeof(double) * 2 * cap);
+        }
+        if (yn[0] * yn[0] + yn[1] * yn[1] >= R * R) {
+            double ax = yn[0] - y[0], ay = yn[1] - y[1];
+            double A = ax * ax + ay * ay;
+            double B = 2.0 * (y[0] * ax + y[1] * ay);
+            double C = y[0] * y[0] + y[1] * y[1] - R * R;
+            double D = B * B - 4.0 * A * C;
+            if (D < 0) D = 0;
+            double t = (B >= 0) ? (-2.0 * C) / (B + sqrt(D)) : (-B + sqrt(D)) / (2.0 * A);
+            if (t > 1.0) t = 1.0;
+            if (t < 0.0) t = 0.0;
+            r->qx = y[0] + t * ax;
+            r->qy = y[1] + t * ay;
+            r->dsp = t * o->ds;
+            pts[2 * n] = r->qx;
+            pts[2 * n + 1] = r->qy;
+            r->M = n;
+            n++;
+            double cq, gqx, gqy;
+            medium_eval(m, r->qx, r->qy, &cq, &gqx, &gqy);
+            r->status = (cq > 0.0) ? ST_LINKED : ST_BAD_INPUT;
+            break;
+        }
+        for (int i = 0; i < 4; i++) y[i] = yn[i];
+        pts[2 * n] = y[0];
+        pts[2 * n + 1] = y[1];
+        n++;
+        r->M = n - 1;
+    }
+    r->pts = pts;
+}
+
+/* Trapezoid weights (pixels) of samples 0..M with partial last step dsp:
+   w0 = ds/2, wm = ds (1 <= m <= M-2), w_{M-1} = (ds + ds')/2, w_M = ds'/2;
+   M = 1: w0 = w1 = ds'/2. */
+static double trap_weight(int mi, int M, double ds, double dsp)
+{
+    if (M == 1) return dsp / 2.0;
+    if (mi == 0) return ds / 2.0;
+    if (mi == M) return dsp / 2.0;
+    if (mi == M - 1) return (ds + dsp) / 2.0;
+    return ds;
+}
+
+/* T = sum w_m h / c(p_m) (seconds), L = ((M-1) ds + ds') h (metres). */
+static void quadrature(const Medium *m, const March *r, double ds, double *T, double *L)
+{
+    double acc = 0.0;
+    for (int i = 0; i <= r->M; i++) {
+        double c, gx, gy;
+        medium_eval(m, r->pts[2 * i], r->pts[2 * i + 1], &c, &gx, &gy);
+        acc += trap_weight(i, r->M, ds, r->dsp) * m->h / c;
+    }
+    *T = acc;
+    *L = ((r->M - 1) * ds + r->dsp) * m->h;
+}
+
+/* ---------------------------------------------------------------- geometry -- */
+static double elem_angle(const Ring *ring, int k)
+{
+    return ring->phi0 + 2.0 * PI * k / ring->n_elem;
+}
+
+/* Emitter-relative unwrapped angular misfit of an interception point. */
+static double misfit(const Ring *ring, int e, int rcv, double qx, double qy)
+{
+    double pe = elem_angle(ring, e), pr = elem_angle(ring, rcv);
+    return mod2pi(atan2(qy, qx) - pe) - mod2pi(pr - pe);
+}
+
+static double straight_angle(const Ring *ring, int e, int rcv)
+{
+    return (mod2pi(elem_angle(ring, rcv) - elem_angle(ring, e)) - PI) / 2.0;
+}
+
+/* ------------------------------------------------------------------ linking -- */
+typedef struct {
+    double theta, T, L, miss;
+    int n_marches, status;
+} LinkOut;
+
+/* Traces one ray of pair (e, rcv) at launch angle theta (relative to the inward
+   normal at e) and returns status, misfit g and T, L of the march. */
+static int trace_at(const Medium *m, const Ring *ring, const Opts *o, int e, int rcv, double theta,
+                    double *g, double *T, double *L, March *keep)
+{
+    double pe = elem_angle(ring, e);
+    double ex = ring->radius_px * cos(pe), ey = ring->radius_px * sin(pe);
+    March r;
+    march(m, ring, o, ex, ey, pe + PI + theta, &r);
+    int st = r.status;
+    if (st == ST_LINKED) {
+        *g = misfit(ring, e, rcv, r.qx, r.qy);
+        quadrature(m, &r, o->ds, T, L);
+    } else {
+        *g = NAN;
+        *T = NAN;
+        *L = NAN;
+    }
+    if (keep)
+        *keep = r;
+    else
+        free(r.pts);
+    return st;
+}
+
+/* Two-point linking of one pair by the safeguarded secant on the launch angle.
+ *   theta_0: straight-ray angle (homogeneous start) or the warm-start value.
+ *   second point: theta_1 = theta_0 - g_0 / 2, the homogeneous-medium Newton step
+ *     (there dg/dtheta = 2); used only to obtain a second point, since a focusing
+ *     medium can reverse the sign of dg/dtheta.
+ *   then secant through the two latest traced angles that hit the ring.
+ * Safeguards:
+ *   (a) theta_neg / theta_pos = latest traced angles with g < 0 / g > 0.  Once
+ *       both exist, a secant iterate outside the open interval between them, or
+ *       a zero secant denominator, is replaced by their midpoint.
+ *   (b) before such a bracket exists, an iterate at or beyond the limits
+ *       +-(pi/2 - 1e-6) is replaced by the midpoint between the current angle
+ *       and that limit; a zero secant denominator falls back to the Newton step.
+ *   (c) a march with no interception (trapped ray) yields no g: the next angle is
+ *       the midpoint with the latest angle that did hit, or half the angle if
+ *       none did.
+ *   (d) the limits +-pi/2 are never assumed to have a known misfit sign.
+ * Stops when miss = |g| R <= tol (LINKED) or after max_marches traced rays
+ * (NOT_CONVERGED, returning the traced ray of smallest miss). */
+static void link_pair(const Medium *m, const Ring *ring, const Opts *o, int e, int rcv, double theta0, LinkOut *out)
+{
+    const double lim = PI / 2.0 - 1e-6;
+    double th = theta0;
+    double tha = 0, ga = 0, thb = 0, gb = 0;
+    int nvalid = 0, have_neg = 0, have_pos = 0;
+    double th_neg = 0, th_pos = 0;
+    double best_miss = INFINITY, best_th = theta0, best_T = NAN, best_L = NAN;
+    int any_bad = 0;
+    out->n_marches = 0;
+    for (int k = 0; k < o->max_marches; k++) {
+        double g, T, L;
+        int st = trace_at(m, ring, o, e, rcv, th, &g, &T, &L, NULL);
+        out->n_marches++;
+        double th_next;
+        if (st == ST_BAD_INPUT) {
+            any_bad = 1;
+            break;
+        }
+        if (st == ST_LINKED) {
+            double miss = fabs(g) * ring->radius_px;
+            if (miss < best_miss) {
+                best_miss = miss;
+                best_th = th;
+                best_T = T;
+                best_L = L;
+            }
+            if (miss <= o->tol) {
+                out->theta = th;
+                out->T = T;
+                out->L = L;
+                out->miss = miss;
+                out->status = ST_LINKED;
+                return;
+            }
+            if (g < 0) {
+                have_neg = 1;
+                th_neg = th;
+            }
+            if (g > 0) {
+                have_pos = 1;
+                th_pos = th;
+            }
+            tha = thb;
+            ga = gb;
+            thb = th;
+            gb = g;
+            nvalid++;
+            int den_zero = 0;
+            if (nvalid == 1) {
+                th_next = th - g / 2.0;
+            } else if (gb - ga == 0.0) {
+                den_zero = 1;
+                th_next = th - g / 2.0;
+            } else {
+                th_next = thb - gb * (thb - tha) / (gb - ga);
+            }
+            if (have_neg && have_pos) {
+                double lo = th_neg < th_pos ? th_neg : th_pos;
+                double hi = th_neg < th_pos ? th_pos : th_neg;
+                if (den_zero || !(th_next > lo && th_next < hi)) th_next = 0.5 * (th_neg + th_pos);
+            } else {
+                if (!(th_next < lim) && th_next == th_next) th_next = 0.5 * (th + lim);
+                if (!(th_next > -lim) && th_next == th_next) th_next = 0.5 * (th - lim);
+                if (!(th_next == th_next)) th_next = 0.5 * th;
+            }
+        } else { /* no interception: back off toward the latest angle that hit */
+            th_next = (nvalid > 0) ? 0.5 * (th + thb) : 0.5 * th;
+        }
+        th = th_next;
+    }
+    if (any_bad) {
+        out->theta = theta0;
+        out->T = NAN;
+        out->L = NAN;
+        out->miss = NAN;
+        out->status = ST_BAD_INPUT;
+        return;
+    }
+    if (best_miss < INFINITY) {
+        out->theta = best_th;
+        out->T = best_T;
+        out->L = best_L;
+        out->miss = best_miss;
+        out->status = ST_NOT_CONVERGED;
+    } else {
+        out->theta = theta0;
+        out->T = NAN;
+        out->L = NAN;
+        out->miss = NAN;
+        out->status = ST_NO_HIT;
+    }
+}
+
+/* --------------------------------------------------------------- exported -- */
+static int setup(int kind, int nx, int ny, double h, const double *c, const double *mpar, int n_elem,
+                 double radius, double phi0, int integ, double ds_px, double tol_px, int max_marches,
+                 int max_steps, int flags, Medium *m, Ring *ring, Opts *o)
+{
+    memset(m, 0, sizeof(*m));
+    m->kind = kind;
+    m->nx = nx;
+    m->ny = ny;
+    m->h = h;
+    m->c = c;
+    for (int i = 0; i < 4; i++) m->p[i] = mpar ? mpar[i] : 0.0;
+    if (kind == OR_GRID) {
+        if (nx < 4 || ny < 4 || !c) return -1;
+        m->gx = (double *)malloc(sizeof(double) * nx * ny);
+        m->gy = (double *)malloc(sizeof(double) * nx * ny);
+        or_gradient(nx, ny, c, m->gx, m->gy);
+    }
+    ring->n_elem = n_elem;
+    ring->radius_px = radius / h;
+    ring->phi0 = phi0;
+    o->integ = integ;
+    o->ds = ds_px;
+    o->tol = tol_px;
+    o->max_marches = max_marches;
+    o->max_steps = max_steps > 0 ? max_steps : (int)ceil(8.0 * ring->radius_px / ds_px);
+    o->flags = flags;
+    return 0;
+}
+
+static void teardown(Medium *m)
+{
+    free(m->gx);
+    free(m->gy);
+}
+
+/* Per pair (e, r): theta [in: warm start / fixed angle | out: linked angle],
+   T (s), L (m), miss (pixels), number of traced rays and status.
+   flags & OPT_FIXED: trace once at the given theta, no linking (status LINKED
+   means "hit the ring"; miss is then the miss of that ray).
+   flags & OPT_WARM: start linking from the given theta instead of the straight
+   ray.  Pairs with e == r or an index outside [0, n_elem) get ST_BAD_INPUT. */
+int or_trace(int kind, int nx, int ny, double h, const double *c, const double *mpar, int n_elem,
+             double radius, double phi0, int integ, double ds_px, double tol_px, int max_marches,
+             int max_steps, int flags, int n_pairs, const int32_t *pairs, double *theta, double *T,
+             double *L, double *miss, int32_t *n_marches, int8_t *status)
+{
+    Medium m;
+    Ring ring;
+    Opts o;
+    if (setup(kind, nx, ny, h, c, mpar, n_elem, radius, phi0, integ, ds_px, tol_px, max_marches, max_steps,
+              flags, &m, &ring, &o))
+        return -1;
+    for (int i = 0; i < n_pairs; i++) {
+        int e = pairs[2 * i], r = pairs[2 * i + 1];
+        if (e == r || e < 0 || r < 0 || e >= n_elem || r >= n_elem) {
+            T[i] = L[i] = miss[i] = NAN;
+            n_marches[i] = 0;
+            status[i] = ST_BAD_INPUT;
+            continue;
+        }
+        if (flags & OPT_FIXED) {
+            double g, Ti, Li;
+            int st = trace_at(&m, &ring, &o, e, r, theta[i], &g, &Ti, &Li, NULL);
+            T[i] = Ti;
+            L[i] = Li;
+            miss[i] = fabs(g) * ring.radius_px;
+            n_marches[i] = 1;
+            status[i] = (int8_t)st;
+            continue;
+        }
+        double th0 = (flags & OPT_WARM) ? theta[i] : straight_angle(&ring, e, r);
+        LinkOut lo;
+        link_pair(&m, &ring, &o, e, r, th0, &lo);
+        theta[i] = lo.theta;
+        T[i] = lo.T;
+        L[i] = lo.L;
+        miss[i] = lo.miss;
+        n_marches[i] = lo.n_marches;
+        status[i] = (int8_t)lo.status;
+    }
+    teardown(&m);
+    return 0;
+}
+
+/* Samples of one fixed-angle march of pair (e, r): writes up to cap points
+   [cap][2] (pixels), the partial step and the misfit; returns M + 1 (number of
+   samples) or -status - 1 when the ray did not hit the ring. */
+int or_march_points(int kind, int nx, int ny, double h, const double *c, const double *mpar, int n_elem,
+                    double radius, double phi0, int integ, double ds_px, int max_steps, int e, int rcv,
+                    double theta, double *pts, int cap, double *dsp, double *g)
+{
+    Medium m;
+    Ring ring;
+    Opts o;
+    if (setup(kind, nx, ny, h, c, mpar, n_elem, radius, phi0, integ, ds_px, 1.0, 1, max_steps, OPT_FIXED, &m,
+              &ring, &o))
+        return -100;
+    double Ti, Li;
+    March r;
+    int st = trace_at(&m, &ring, &o, e, rcv, theta, g, &Ti, &Li, &r);
+    int n = r.M + 1;
+    for (int i = 0; i < n && i < cap; i++) {
+        pts[2 * i] = r.pts[2 * i];
+        pts[2 * i + 1] = r.pts[2 * i + 1];
+    }
+    *dsp = r.dsp;
+    free(r.pts);
+    teardown(&m);
+    return st == ST_LINKED ? n : -st - 1;
+}
+
+/* Free march (no ring): n_steps steps from pixel point x0 with direction d0,
+   writing the n_steps + 1 points (pixels) into pts.  Used for the fish-eye
+   trajectory experiments, where rays are followed over a full circle. */
+int or_march_free(int kind, int nx, int ny, double h, const double *c, const double *mpar, int integ,
+                  double ds_px, const double *x0, const double *d0, int n_steps, double *pts)
+{
+    Medium m;
+    Ring ring;
+    Opts o;
+    if (setup(kind, nx, ny, h, c, mpar, 4, 1.0 * h, 0.0, integ, ds_px, 1.0, 1, 1, 0, &m, &ring, &o)) return -1;
+    double y[4] = {x0[0], x0[1], d0[0], d0[1]}, yn[4];
+    double nrm = sqrt(y[2] * y[2] + y[3] * y[3]);
+    y[2] /= nrm;
+    y[3] /= nrm;
+    pts[0] = y[0];
+    pts[1] = y[1];
+    for (int i = 1; i <= n_steps; i++) {
+        step(&m, integ, ds_px, y, yn);
+        for (int j = 0; j < 4; j++) y[j] = yn[j];
+        pts[2 * i] = y[0];
+        pts[2 * i + 1] = y[1];
+    }
+    teardown(&m);
+    return 0;
+}
+
+/* Interpolated c and per-pixel gradient at n pixel points. */
+int or_interp(int kind, int nx, int ny, double h, const double *c, const double *mpar, int n, const double *pts,
+              double *cv, double *gxv, double *gyv)
+{
+    Medium m;
+    Ring ring;
+    Opts o;
+    if (setup(kind, nx, ny, h, c, mpar, 4, 1.0 * h, 0.0, 4, 0.25, 1.0, 1, 1, 0, &m, &ring, &o)) return -1;
+    for (int i = 0; i < n; i++) medium_eval(&m, pts[2 * i], pts[2 * i + 1], &cv[i], &gxv[i], &gyv[i]);
+    teardown(&m);
+    return 0;
+}
+
+static int cmp_int(const void *a, const void *b)
+{
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+/* One system-matrix row of pair (e, r) traced at the fixed angle theta:
+   W_j = sum_m w_m h phi_j(p_m) (metres), merged per node and sorted by node
+   index j = iy * nx + ix.  Grid media only.  Returns the number of nonzeros
+   (written only when <= cap), or a negative value if the ray did not hit. */
+long or_weights_row(int nx, int ny, double h, const double *c, int n_elem, double radius, double phi0, int integ,
+                    double ds_px, int max_steps, int e, int rcv, double theta, int32_t *cols, double *vals,
+                    long cap)
+{
+    Medium m;
+    Ring ring;
+    Opts o;
+    if (setup(OR_GRID, nx, ny, h, c, NULL, n_elem, radius, phi0, integ, ds_px, 1.0, 1, max_steps, OPT_FIXED, &m,
+              &ring, &o))
+        return -100;
+    double g, Ti, Li;
+    March r;
+    int st = trace_at(&m, &ring, &o, e, rcv, theta, &g, &Ti, &Li, &r);
+    if (st != ST_LINKED) {
+        free(r.pts);
+        teardown(&m);
+        return -1 - st;
+    }
+    double *dense = (double *)calloc((size_t)nx * ny, sizeof(double));
+    int *touched = (int *)malloc(sizeof(int) * 4 * (r.M + 1));
+    char *mark = (char *)calloc((size_t)nx * ny, 1);
+    int nt = 0;
+    for (int i = 0; i <= r.M; i++) {
+        int ix, iy;
+        double t, s, w[4];
+        locate(&m, r.pts[2 * i], r.pts[2 * i + 1], &ix, &iy, &t, &s);
+        hat4(t, s, w);
+        int nodes[4] = {iy * nx + ix, iy * nx + ix + 1, (iy + 1) * nx + ix, (iy + 1) * nx + ix + 1};
+        double wm = trap_weight(i, r.M, ds_px, r.dsp) * h;
+        for (int k = 0; k < 4; k++) {
+            if (w[k] == 0.0) continue;
+            dense[nodes[k]] += wm * w[k];
+            if (!mark[nodes[k]]) {
+                mark[nodes[k]] = 1;
+                touched[nt++] = nodes[k];
+            }
+        }
+    }
+    qsort(touched, nt, sizeof(int), cmp_int);
+    if (nt <= cap) {
+        for (int k = 0; k < nt; k++) {
+            cols[k] = touched[k];
+            vals[k] = dense[touched[k]];
+        }
+    }
+    free(dense);
+    free(touched);
+    free(mark);
+    free(r.pts);
+    teardown(&m);
+    return nt;
+}
+
+/* Adjoint of the path weights: grad_j += sum_i rho_i sum_m w_m h kappa_m phi_j(p_m)
+   with kappa = 1 (weight_mode 0: transpose of the system matrix) or
+   kappa = -1 / c(p_m)^2 (weight_mode 1: frozen-path derivative of T with respect
+   to the node sound speeds).  Each pair is traced once at its fixed theta.
+   Pairs whose ray does not hit the ring contribute nothing, and so do pairs
+   whose status (if given) is neither LINKED nor NOT_CONVERGED -- the two cases
+   where theta is a traced ray that hit.  Summed in FP64 in pair order. */
+int or_adjoint(int nx, int ny, double h, const double *c, int n_elem, double radius, double phi0, int integ,
+               double ds_px, int max_steps, int n_pairs, const int32_t *pairs, const double *theta,
+               const int8_t *status, const double *rho, int weight_mode, double *grad)
+{
+    Medium m;
+    Ring ring;
+    Opts o;
+    if (setup(OR_GRID, nx, ny, h, c, NULL, n_elem, radius, phi0, integ, ds_px, 1.0, 1, max_steps, OPT_FIXED, &m,
+              &ring, &o))
+        return -1;
+    for (int p = 0; p < n_pairs; p++) {
+        int e = pairs[2 * p], rc = pairs[2 * p + 1];
+        if (e == rc || e < 0 || rc < 0 || e >= n_elem || rc >= n_elem) continue;
+        if (status && status[p] != ST_LINKED && status[p] != ST_NOT_CONVERGED) continue;
+        double g, Ti, Li;
+        March r;
+        int st = trace_at(&m, &ring, &o, e, rc, theta[p], &g, &Ti, &Li, &r);
+        if (st == ST_LINKED) {
+            for (int i = 0; i <= r.M; i++) {
+                int ix, iy;
+                double t, s, w[4];
+                locate(&m, r.pts[2 * i], r.pts[2 * i + 1], &ix, &iy, &t, &s);
+                hat4(t, s, w);
+                double kappa = 1.0;
+                if (weight_mode == 1) {
+                    double cc, gx, gy;
+                    medium_eval(&m, r.pts[2 * i], r.pts[2 * i + 1], &cc, &gx, &gy);
+                    kappa = -1.0 / (cc * cc);
+                }
+                double a = rho[p] * trap_weight(i, r.M, ds_px, r.dsp) * h * kappa;
+                grad[iy * nx + ix] += a * w[0];
+                grad[iy * nx + ix + 1] += a * w[1];
+                grad[(iy + 1) * nx + ix] += a * w[2];
+                grad[(iy + 1) * nx + ix + 1] += a * w[3];
+            }
+        }
+        free(r.pts);
+    }
+    teardown(&m);
+    return 0;
+}
+
+/* Ray-Born-style residual reduction for phase-linearised data d_k = exp(i w_k T):
+   the adjoint of dd_k = i w_k exp(i w_k T) dT applied to residuals r_k is
+   rho = sum_k Re[ conj(i w_k exp(i w_k T)) r_k ] = sum_k w_k Im(exp(-i w_k T) r_k),
+   w_k = 2 pi f_k.  resid is interleaved (re, im) [n][n_freq][2]. */
+int or_rayborn_rho(int n, int n_freq, const double *T, const double *freqs, const double *resid, double *rho)
+{
+    for (int i = 0; i < n; i++) {
+        double acc = 0.0;
+        for (int k = 0; k < n_freq; k++) {
+            double w = 2.0 * PI * freqs[k];
+            double ph = fmod(w * T[i], 2.0 * PI);
+            double re = resid[2 * ((size_t)i * n_freq + k)], im = resid[2 * ((size_t)i * n_freq + k) + 1];
+            /* exp(-i ph) (re + i im) = (re cos ph + im sin ph) + i (im cos ph - re sin ph) */
+            acc += w * (im * cos(ph) - re * sin(ph));
+        }
+        rho[i] = acc;
+    }
+    return 0;
+}

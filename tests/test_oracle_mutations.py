@@ -1,0 +1,69 @@
+"""The oracle's pins must catch plausible mistakes: each case below plants one
+(a flipped sign, a dropped term, transposed axes or operands, a wrong
+quadrature weight or integrator coefficient, a wrong misfit or start angle) in
+a copy of the oracle source, builds it, and expects some pin to fail."""
+import os
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as P
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle_rt.c")
+
+MUTATIONS = {
+    "rhs_sign": ("k[2] = -(gx - gd * y[2]) / c;", "k[2] = (gx - gd * y[2]) / c;"),
+    "rhs_dropped_projection": ("k[3] = -(gy - gd * y[3]) / c;", "k[3] = -(gy) / c;"),
+    "gradient_transposed": ("gx[iy * nx + ix] = d;", "gy[iy * nx + ix] = d;"),
+    "hat_operands_swapped": ("w[1] = t * (1.0 - s);\n    w[2] = (1.0 - t) * s;",
+                             "w[1] = (1.0 - t) * s;\n    w[2] = t * (1.0 - s);"),
+    "trapezoid_last_weight": ("if (mi == M - 1) return (ds + dsp) / 2.0;", "if (mi == M - 1) return ds;"),
+    "rk4_coefficient": ("2.0 * k3[i] + k4[i]", "k3[i] + k4[i]"),
+    "heun_combination": ("out[i] = y[i] + ds / 2.0 * (k1[i] + k2[i]);", "out[i] = y[i] + ds * k2[i];"),
+    "misfit_sign": ("return mod2pi(atan2(qy, qx) - pe) - mod2pi(pr - pe);",
+                    "return mod2pi(pr - pe) - mod2pi(atan2(qy, qx) - pe);"),
+    "straight_angle_offset": ("return (mod2pi(elem_angle(ring, rcv) - elem_angle(ring, e)) - PI) / 2.0;",
+                              "return (mod2pi(elem_angle(ring, rcv) - elem_angle(ring, e)) - PI) / 2.0 + 0.01;"),
+    "edge_stencil": ("d = (-3.0 * c[iy * nx + 0] + 4.0 * c[iy * nx + 1] - c[iy * nx + 2]) / 2.0;",
+                     "d = c[iy * nx + 1] - c[iy * nx + 0];"),
+    "dtdc_kappa": ("kappa = -1.0 / (cc * cc);", "kappa = -1.0 / cc;"),
+    "rayborn_sign": ("acc += w * (im * cos(ph) - re * sin(ph));", "acc += w * (im * cos(ph) + re * sin(ph));"),
+}
+
+PINS = [
+    lambda o: P.test_gradient_exact_on_quadratics(o),
+    lambda o: P.test_gradient_is_not_transposed(o),
+    lambda o: P.test_bilinear_exact_and_gradient_of_quadratic(o),
+    lambda o: P.test_homogeneous_straight_rays(o),
+    lambda o: P.test_homogeneous_weights_are_hat_line_integrals(o),
+    lambda o: P.test_linear_gradient_closed_form(o, (250.0, 300.0), "rk4"),
+    lambda o: P.test_linear_gradient_closed_form(o, (400.0, 0.0), "heun"),
+    lambda o: P.test_weak_medium_links_in_two_marches(o),
+    lambda o: P.test_fisheye_analytic_medium_closed_form(o),
+    lambda o: P.test_paper_fisheye_acoustic_length(o, "analytic", "rk4"),
+    lambda o: P.test_paper_fisheye_radius_deviation(o, "analytic", "rk4"),
+    lambda o: P.test_paper_fisheye_radius_deviation(o, "analytic", "heun"),
+    lambda o: P.test_linear_gradient_second_order_in_step(o),
+    lambda o: P.test_adjoint_is_transpose_of_weights(o),
+    lambda o: P.test_dtdc_adjoint_matches_finite_differences(o),
+    lambda o: P.test_rayborn_rho_is_derivative_of_phase_data(o),
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, tmp_path, orc):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    mut = tmp_path / "oracle_mut.c"
+    mut.write_text(src.replace(old, new))
+    lib = oracle.build(src=str(mut), out=str(tmp_path / "liboracle_mut.so"))
+    caught = None
+    with oracle.use_library(lib):
+        for k, pin in enumerate(PINS):
+            try:
+                pin(oracle)
+            except (AssertionError, ValueError, IndexError, ZeroDivisionError):
+                caught = k
+                break
+    assert caught is not None, f"no pin fails with the planted mistake {name!r}"

@@ -1,0 +1,388 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix:
+closed-form rays (homogeneous, linear gradient, Maxwell fish-eye), the paper's
+fish-eye experiments (Section 4), exactness of the interpolation, reciprocity,
+symmetry, convergence order, a brute-force root scan and finite differences."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests import closed_form as cf
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ------------------------------------------------------------ interpolation --
+def test_gradient_exact_on_quadratics(orc):
+    ny, nx = 7, 9
+    iy, ix = np.mgrid[0:ny, 0:nx].astype(float)
+    c = 3 + 2 * ix - 5 * iy + 0.7 * ix * ix - 0.3 * ix * iy + 1.1 * iy * iy
+    gx, gy = orc.gradient(c)
+    np.testing.assert_allclose(gx, 2 + 1.4 * ix - 0.3 * iy, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(gy, -5 - 0.3 * ix + 2.2 * iy, rtol=0, atol=1e-12)
+
+
+def test_gradient_is_not_transposed(orc):
+    ny, nx = 5, 8
+    iy, ix = np.mgrid[0:ny, 0:nx].astype(float)
+    gx, gy = orc.gradient(10 + ix)  # varies along x (the ix axis) only
+    np.testing.assert_allclose(gx, 1.0, atol=1e-14)
+    np.testing.assert_allclose(gy, 0.0, atol=1e-14)
+
+
+def test_bilinear_exact_and_gradient_of_quadratic(orc):
+    """Bilinear interpolation reproduces a bilinear field exactly; the node
+    gradient of a quadratic is exact and linear, so its interpolation equals
+    the true gradient everywhere (including edge cells)."""
+    ny, nx, h = 11, 14, 1e-3
+    X, Y = synth.node_coords(nx, ny, h)
+    px, py = X / h, Y / h
+    rng = np.random.default_rng(0)
+    pts = np.stack([rng.uniform(px.min(), px.max(), 200), rng.uniform(py.min(), py.max(), 200)], 1)
+    cb = 1500 + 3 * px + 2 * py + 0.5 * px * py
+    cv, _, _ = orc.interp(orc.grid_medium(cb, h), pts)
+    np.testing.assert_allclose(cv, 1500 + 3 * pts[:, 0] + 2 * pts[:, 1] + 0.5 * pts[:, 0] * pts[:, 1],
+                               rtol=1e-14)
+    cq = 1500 + 3 * px - 2 * py + 0.25 * px * px + 0.1 * px * py - 0.2 * py * py
+    _, gxv, gyv = orc.interp(orc.grid_medium(cq, h), pts)
+    np.testing.assert_allclose(gxv, 3 + 0.5 * pts[:, 0] + 0.1 * pts[:, 1], rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(gyv, -2 + 0.1 * pts[:, 0] - 0.4 * pts[:, 1], rtol=1e-13, atol=1e-12)
+
+
+# ------------------------------------------------------------ homogeneous --
+def test_homogeneous_straight_rays(orc):
+    n, h, c0 = 64, 1e-3, 1500.0
+    ring = (16, 0.025, 0.3)
+    pairs = synth.all_pairs(16)
+    o = orc.trace(orc.grid_medium(synth.homogeneous(n, n, c0), h), ring, pairs)
+    pts, _ = cf.ring_points(*ring)
+    for i, (e, r) in enumerate(pairs):
+        T, L = cf.homogeneous(pts[e], pts[r], c0)
+        assert abs(o["tof"][i] / T - 1) < 1e-12
+        assert abs(o["len"][i] / L - 1) < 1e-12
+    assert np.all(o["status"] == orc.LINKED)
+    assert np.all(o["n_marches"] == 1)  # the straight-ray start is already linked
+    assert o["miss_px"].max() < 1e-9
+
+
+def test_homogeneous_weights_are_hat_line_integrals(orc):
+    """Sum_j W_ij = L_i, W >= 0, and W converges at second order to the exact
+    line integrals of the bilinear hats along the straight chord."""
+    n, h, c0 = 40, 1e-3, 1500.0
+    ring = (8, 0.015, 0.1)
+    c = synth.homogeneous(n, n, c0)
+    pts, ang = cf.ring_points(*ring)
+    errs = []
+    for ds in (1 / 16, 1 / 32):
+        e, r = 1, 4
+        theta = (((ang[r] - ang[e]) % (2 * math.pi)) - math.pi) / 2
+        cols, vals = orc.weights_row(c, h, ring, e, r, theta, ds_px=ds)
+        L = np.linalg.norm(pts[r] - pts[e])
+        assert abs(vals.sum() / L - 1) < 1e-12
+        assert np.all(vals >= 0) and np.all(np.diff(cols) > 0)
+        exact = cf.hat_line_integrals(pts[e] / h, pts[r] / h, n, n)
+        dense = np.zeros(n * n)
+        dense[cols] = vals / h
+        ex = np.zeros(n * n)
+        for k, v in exact.items():
+            ex[k] = v
+        errs.append(np.abs(dense - ex).max() / ex.max())
+    assert errs[1] < 2e-3
+    assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+# --------------------------------------------------------- linear gradient --
+@pytest.mark.parametrize("integ", ["rk4", "heun"])
+@pytest.mark.parametrize("G", [(400.0, 0.0), (0.0, -400.0), (250.0, 300.0)])
+def test_linear_gradient_closed_form(orc, G, integ):
+    """c = c0 + G.x is reproduced exactly by the grid (bilinear c, exact node
+    gradient), so the gridded oracle must match the analytic circular rays.
+    A non-square grid catches transposed axes."""
+    nx, ny, h, c0 = 96, 80, 0.5e-3, 1500.0
+    c = synth.linear_gradient(nx, ny, h, c0, *G)
+    ring = (12, 0.018, 0.2)
+    pairs = synth.all_pairs(12)
+    o = orc.trace(orc.grid_medium(c, h), ring, pairs, tol_px=1e-10, integ=integ)
+    pts, _ = cf.ring_points(*ring)
+    assert np.all(o["status"] == orc.LINKED)
+    for i, (e, r) in enumerate(pairs):
+        T = cf.linear_tof(pts[e], pts[r], c0, G)
+        L, th = cf.linear_path(pts[e], pts[r], c0, G)
+        assert abs(o["tof"][i] / T - 1) < 1e-9, (e, r)
+        assert abs(o["len"][i] / L - 1) < 1e-9, (e, r)
+        # the last step is cut on a chord, an O(ds^2) endpoint shift
+        assert abs(o["theta"][i] - th) < 1e-6, (e, r)
+
+
+def test_weak_medium_links_in_two_marches(orc):
+    """In a weakly refracting medium the misfit is close to its homogeneous form
+    g = 2 (theta - theta*), so the straight-ray start plus one homogeneous Newton
+    step already links every pair at a 1e-3 px tolerance."""
+    nx, ny, h, c0 = 96, 80, 0.5e-3, 1500.0
+    c = synth.linear_gradient(nx, ny, h, c0, 250.0, 300.0)
+    o = orc.trace(orc.grid_medium(c, h), (12, 0.018, 0.2), synth.all_pairs(12), tol_px=1e-3)
+    assert np.all(o["status"] == orc.LINKED)
+    assert np.all(o["n_marches"] == 2)
+
+
+def test_linear_gradient_second_order_in_step(orc):
+    nx = ny = 96
+    h, c0, G = 0.5e-3, 1500.0, (500.0, 0.0)
+    c = synth.linear_gradient(nx, ny, h, c0, *G)
+    ring = (8, 0.018, 0.0)
+    pairs = np.array([[0, 3], [1, 5], [2, 7]], dtype=np.int32)
+    pts, _ = cf.ring_points(*ring)
+    exact = np.array([cf.linear_tof(pts[e], pts[r], c0, G) for e, r in pairs])
+    err = []
+    for ds in (1.0, 0.5, 0.25):
+        o = orc.trace(orc.grid_medium(c, h), ring, pairs, ds_px=ds, tol_px=1e-11)
+        err.append(np.abs(o["tof"] / exact - 1))
+    r1, r2 = err[0] / err[1], err[1] / err[2]
+    assert np.all(np.abs(r1 / 4 - 1) < 0.15) and np.all(np.abs(r2 / 4 - 1) < 0.15)
+
+
+# -------------------------------------------------------------- fish-eye --
+def test_fisheye_analytic_medium_closed_form(orc):
+    """Analytic fish-eye (no grid): rays are arcs of the circle through e, r and
+    e*; T from the stereographic map.  Only integrator + quadrature error."""
+    cfg = synth.CONFIGS["c1_fisheye_128"]
+    med = {"kind": "fisheye", "nx": 128, "ny": 128, "h": cfg["h"], "c0": 1500.0, "R": 0.040}
+    ring = (32, cfg["radius"], 0.0)
+    pairs = synth.all_pairs(32)[:31]  # emitter 0 to every receiver
+    o = orc.trace(med, ring, pairs, tol_px=1e-3)
+    pts, _ = cf.ring_points(*ring)
+    assert np.all(o["status"] == orc.LINKED)
+    for i, (e, r) in enumerate(pairs):
+        T = cf.fisheye_tof(pts[e], pts[r], 1500.0, 0.040)
+        L, th = cf.fisheye_path(pts[e], pts[r], 0.040)
+        assert abs(o["tof"][i] / T - 1) < 5e-6, (e, r)
+        assert abs(o["len"][i] / L - 1) < 5e-5, (e, r)
+        assert abs(o["theta"][i] - th) < 1e-3, (e, r)
+
+
+def test_fisheye_gridded_config(orc):
+    """The 128x128, 1 mm gridded fish-eye: bias of bilinear c is at most
+    c0 h^2 / (2 R^2) relative."""
+    cfg, c = synth.make_config("c1_fisheye_128")
+    ring = (32, cfg["radius"], 0.0)
+    pairs = synth.all_pairs(32)
+    o = orc.trace(orc.grid_medium(c, cfg["h"]), ring, pairs)
+    pts, _ = cf.ring_points(*ring)
+    assert np.all(o["status"] == orc.LINKED)
+    T = np.array([cf.fisheye_tof(pts[e], pts[r], 1500.0, 0.040) for e, r in pairs])
+    assert np.max(np.abs(o["tof"] / T - 1)) < 5e-4
+    assert np.all(o["n_marches"] <= 12)
+
+
+def _golden():
+    with open(os.path.join(HERE, "golden", "fisheye_paper.json")) as f:
+        return json.load(f)
+
+
+# Bounds at ds/dx = 1 for the two integrators (percent).  The paper shows its
+# deviations only as plots; these bounds are this implementation's error budget:
+# analytic medium = integrator + quadrature error, grid = plus bilinear bias.
+RE_AL_MAX = {("rk4", "analytic"): 0.003, ("heun", "analytic"): 0.005,
+             ("rk4", "grid"): 0.02, ("heun", "grid"): 0.02}
+RE_RD_MAX = {("rk4", "analytic"): 1e-5, ("heun", "analytic"): 0.02,
+             ("rk4", "grid"): 0.02, ("heun", "grid"): 0.03}
+
+
+def _fisheye_medium(orc, kind, n, dx, a):
+    if kind == "grid":
+        return orc.grid_medium(synth.fisheye(n, n, dx, c0=1.0, R=a), dx)
+    return {"kind": "fisheye", "nx": n, "ny": n, "h": dx, "c0": 1.0, "R": a}
+
+
+@pytest.mark.parametrize("integ", ["rk4", "heun"])
+@pytest.mark.parametrize("kind", ["analytic", "grid"])
+def test_paper_fisheye_acoustic_length(orc, kind, integ):
+    """Section 4.2: 101 rays from [0, a] over theta in [-pi/3, pi/3] all reach
+    [0, -a] with acoustic length a pi / 2 (2-D).  With c0 = n0 = 1 the travel
+    time equals the acoustic length."""
+    g = _golden()
+    a, dx = g["a"], g["dx_over_a"] * g["a"]
+    ds = g["ds_over_dx"]
+    n = 2 * int(math.ceil(1.1 * a / dx)) + 1
+    med = _fisheye_medium(orc, kind, n, dx, a)
+    ring = (4, a, math.pi / 2)  # element 0 at x_p = [0, a], element 2 at [0, -a]
+    th = np.linspace(*g["al_theta_range"], g["al_n_rays"])
+    pairs = np.tile(np.array([[0, 2]], np.int32), (len(th), 1))
+    o = orc.trace(med, ring, pairs, theta=th, ds_px=ds, fixed=True, integ=integ)
+    assert np.all(o["status"] == orc.LINKED)
+    re_al = np.mean((o["tof"] - g["L_true"]) / g["L_true"]) * 100
+    assert abs(re_al) < RE_AL_MAX[(integ, kind)]
+    # every ray is intercepted at [0, -a]; the last step is cut on a chord, O(ds^2)
+    assert np.max(o["miss_px"]) * dx < 2e-4 * a
+
+
+@pytest.mark.parametrize("integ", ["rk4", "heun"])
+@pytest.mark.parametrize("kind", ["analytic", "grid"])
+def test_paper_fisheye_radius_deviation(orc, kind, integ):
+    """Section 4.1: the ray from [0, a] launched clockwise normal to x_c - x_p
+    circles x_c = [a, 0] with radius sqrt(2) a; p* is the first point back
+    within ds of x_p."""
+    g = _golden()
+    a, dx = g["a"], g["dx_over_a"] * g["a"]
+    ds = g["ds_over_dx"]
+    n = 2 * int(math.ceil(2.6 * a / dx)) + 1
+    med = _fisheye_medium(orc, kind, n, dx, a)
+    x0 = np.array(g["rd_start"]) / dx
+    circ = 2 * math.pi * g["R_true"] / dx
+    pts = orc.march_free(med, x0, g["rd_direction_clockwise"], int(1.2 * circ / ds), ds_px=ds, integ=integ)
+    dist0 = np.linalg.norm(pts - x0, axis=1)
+    far = np.nonzero(dist0 > 10 * ds)[0][0]
+    M = far + np.nonzero(dist0[far:] < ds)[0][0]
+    rad = np.linalg.norm(pts[1:M + 1] * dx - np.array(g["rd_centre"]), axis=1)
+    re_rd = np.mean(np.abs(rad - g["R_true"]) / g["R_true"]) * 100
+    assert re_rd < RE_RD_MAX[(integ, kind)]
+    # the ray went clockwise around x_c (negative signed area)
+    area = 0.5 * np.sum(pts[:M, 0] * pts[1:M + 1, 1] - pts[1:M + 1, 0] * pts[:M, 1])
+    assert area < 0
+
+
+# -------------------------------------------------------- invariants --------
+def test_reciprocity_gaussian_medium(orc):
+    """Backward rays are the reversed forward rays (Appendix): T(e,r) = T(r,e)."""
+    n, h = 128, 0.5e-3
+    c = synth.gaussian_inclusions(n, n, h, seed=7, r_max=0.022)
+    ring = (24, 0.030, 0.05)
+    pairs = synth.all_pairs(24)
+    idx = {(int(e), int(r)): i for i, (e, r) in enumerate(pairs)}
+    gaps = []
+    for ds in (0.25, 0.125):
+        o = orc.trace(orc.grid_medium(c, h), ring, pairs, tol_px=1e-10, ds_px=ds)
+        assert np.all(o["status"] == orc.LINKED)
+        gaps.append(max(abs(o["tof"][i] / o["tof"][idx[(r, e)]] - 1) for (e, r), i in idx.items()))
+    # the discrete forward and backward rays differ by discretisation error only,
+    # which must shrink at (about) second order in the step
+    assert gaps[0] < 1e-6 and gaps[0] / gaps[1] > 3.0
+
+
+def test_d4_symmetry_fisheye(orc):
+    """A radially symmetric grid medium with n_elem divisible by 4: T is
+    invariant under 90-degree rotations and the reflection y -> -y."""
+    cfg, c = synth.make_config("c1_fisheye_128")
+    ring = (32, cfg["radius"], 0.0)
+    pairs = synth.all_pairs(32)
+    o = orc.trace(orc.grid_medium(c, cfg["h"]), ring, pairs, tol_px=1e-10)
+    T = {(int(e), int(r)): o["tof"][i] for i, (e, r) in enumerate(pairs)}
+    for (e, r), t in T.items():
+        assert abs(T[((e + 8) % 32, (r + 8) % 32)] / t - 1) < 1e-10
+        assert abs(T[((-e) % 32, (-r) % 32)] / t - 1) < 1e-10
+
+
+def test_linking_root_matches_bruteforce_scan(orc):
+    """A dense scan of the signed misfit over launch angles: the linked angle
+    lies in a scanned sign-change interval, i.e. it is a root of g."""
+    n, h = 32, 1e-3
+    c = synth.gaussian_inclusions(n, n, h, seed=3, amp=80.0, sigma=(0.002, 0.004), r_max=0.008)
+    ring = (8, 0.012, 0.0)
+    med = orc.grid_medium(c, h)
+    pairs = np.array([[0, 3], [2, 5], [6, 1]], np.int32)
+    lk = orc.trace(med, ring, pairs, tol_px=1e-9)
+    lim = math.pi / 2 - 1e-3
+    th = np.linspace(-lim, lim, 2001)
+    for k, (e, r) in enumerate(pairs):
+        g = np.array([orc.march_points(med, ring, e, r, t)[2] for t in th])
+        ok = np.isfinite(g[:-1]) & np.isfinite(g[1:])
+        roots = np.nonzero(ok & (np.sign(g[:-1]) * np.sign(g[1:]) <= 0))[0]
+        assert lk["status"][k] == orc.LINKED
+        t_star = lk["theta"][k]
+        assert np.any((th[roots] <= t_star) & (t_star <= th[roots + 1])), (e, r, t_star, th[roots])
+
+
+# ------------------------------------------------------------ failure paths --
+def test_status_paths(orc):
+    n, h = 64, 1e-3
+    c = synth.gaussian_inclusions(n, n, h, seed=11, r_max=0.015)
+    ring = (16, 0.025, 0.0)
+    med = orc.grid_medium(c, h)
+    pairs = np.array([[0, 5], [3, 3], [2, 16], [-1, 4]], np.int32)
+    o = orc.trace(med, ring, pairs)
+    assert list(o["status"][1:]) == [orc.BAD_INPUT] * 3
+    o1 = orc.trace(med, ring, pairs[:1], max_marches=1)
+    assert o1["status"][0] in (orc.LINKED, orc.NOT_CONVERGED) and o1["n_marches"][0] == 1
+    o2 = orc.trace(med, ring, pairs[:1], tol_px=0.0, max_marches=4)
+    assert o2["status"][0] == orc.NOT_CONVERGED and o2["n_marches"][0] == 4
+    assert np.isfinite(o2["tof"][0])
+    o3 = orc.trace(med, ring, pairs[:1], max_steps=3)
+    assert o3["status"][0] == orc.NO_HIT and np.isnan(o3["tof"][0])
+    cb = c.copy()
+    cb[32, 30:34] = np.nan
+    o4 = orc.trace(orc.grid_medium(cb, h), ring, np.array([[0, 8]], np.int32))
+    assert o4["status"][0] == orc.BAD_INPUT
+    cz = c.copy()
+    cz[30:34, 30:34] = -1.0
+    o5 = orc.trace(orc.grid_medium(cz, h), ring, np.array([[0, 8]], np.int32))
+    assert o5["status"][0] == orc.BAD_INPUT
+
+
+# --------------------------------------------------------------- adjoint --
+def test_adjoint_is_transpose_of_weights(orc):
+    n, h = 48, 1e-3
+    c = synth.gaussian_inclusions(n, n, h, seed=5, r_max=0.012)
+    ring = (10, 0.018, 0.0)
+    pairs = synth.all_pairs(10)
+    lk = orc.trace(orc.grid_medium(c, h), ring, pairs)
+    rowptr, cols, vals = orc.weights_csr(c, h, ring, pairs, lk["theta"])
+    L_rows = np.add.reduceat(vals, rowptr[:-1])
+    np.testing.assert_allclose(L_rows, lk["len"], rtol=1e-12)
+    rng = np.random.default_rng(1)
+    s = rng.standard_normal(n * n)
+    rho = rng.standard_normal(len(pairs))
+    Ws = np.array([vals[rowptr[i]:rowptr[i + 1]] @ s[cols[rowptr[i]:rowptr[i + 1]]] for i in range(len(pairs))])
+    WTr = orc.adjoint(c, h, ring, pairs, lk["theta"], rho, weight="length").ravel()
+    assert abs(Ws @ rho - s @ WTr) <= 1e-12 * abs(s @ WTr) + 1e-15
+    # for a homogeneous medium, W (1/c0) is the travel time
+    ch = synth.homogeneous(n, n, 1500.0)
+    lh = orc.trace(orc.grid_medium(ch, h), ring, pairs)
+    rp, cc, vv = orc.weights_csr(ch, h, ring, pairs, lh["theta"])
+    np.testing.assert_allclose(np.add.reduceat(vv, rp[:-1]) / 1500.0, lh["tof"], rtol=1e-12)
+
+
+def test_dtdc_adjoint_matches_finite_differences(orc):
+    """Frozen-path (Fermat) derivative of the linked T with respect to node
+    sound speeds against central differences of the linked T."""
+    n, h = 64, 0.5e-3
+    c = synth.gaussian_inclusions(n, n, h, seed=9, r_max=0.012)
+    ring = (12, 0.014, 0.0)
+    pairs = synth.all_pairs(12)
+    med = orc.grid_medium(c, h)
+    lk = orc.trace(med, ring, pairs, tol_px=1e-10)
+    rng = np.random.default_rng(2)
+    rho = rng.standard_normal(len(pairs))
+    grad = orc.adjoint(c, h, ring, pairs, lk["theta"], rho, weight="dtdc")
+    cand = np.argwhere(np.abs(grad) > 0.1 * np.abs(grad).max())
+    pick = cand[rng.choice(len(cand), 8, replace=False)]
+    eps = 0.5
+    for iy, ix in pick:
+        cp, cm = c.copy(), c.copy()
+        cp[iy, ix] += eps
+        cm[iy, ix] -= eps
+        Tp = orc.trace(orc.grid_medium(cp, h), ring, pairs, theta=lk["theta"], warm=True, tol_px=1e-10)["tof"]
+        Tm = orc.trace(orc.grid_medium(cm, h), ring, pairs, theta=lk["theta"], warm=True, tol_px=1e-10)["tof"]
+        fd = rho @ (Tp - Tm) / (2 * eps)
+        assert abs(fd - grad[iy, ix]) <= 1e-2 * abs(grad[iy, ix]), (iy, ix, fd, grad[iy, ix])
+
+
+def test_rayborn_rho_is_derivative_of_phase_data(orc):
+    """rho = d/dT Re sum_k conj(exp(i w_k T)) r_k for phase-linearised data."""
+    rng = np.random.default_rng(4)
+    n, nf = 5, 64
+    T = rng.uniform(5e-5, 1.5e-4, n)
+    f = np.linspace(0.5e6, 1.5e6, nf)
+    r = synth.complex_residual(n, nf, 4)
+    rho = orc.rayborn_rho(T, f, r)
+    w = 2 * np.pi * f
+
+    def F(t, i):
+        return np.real(np.sum(np.conj(np.exp(1j * w * t)) * r[i].astype(np.complex128)))
+
+    for i in range(n):
+        dt = 1e-12
+        fd = (F(T[i] + dt, i) - F(T[i] - dt, i)) / (2 * dt)
+        assert abs(fd - rho[i]) < 1e-5 * np.abs(rho).max()
