@@ -1,0 +1,191 @@
+"""Benchmark: linked ray tracing (travel time + path length) plus the adjoint
+A^T r on the 256x256 Gaussian-inclusion ring workload (0.5 mm pixels, 256
+elements on a 60 mm ring, 65,280 ordered pairs, RK4 at 0.25 px, 1e-3 px linking
+tolerance), FP32-compensated (headline) and plain FP64, on one GPU.
+
+One step = pack the medium (node gradient + cell coefficients) -> linked trace
+of every pair from straight-ray starts -> adjoint of the path weights for a
+residual r ~ N(0, (1e-4 s)^2).  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+WORKLOAD = "c2_gauss_256"
+# algorithmic cost of one RK4 step of one ray: 4 stages x 4
+# cell corners x 3 fields of gathered medium values, and the FP32 flops of the
+# interpolation, ray equation, RK4 combination, renormalisation and quadrature
+GATHER_VALUES_PER_STEP = 4 * 4 * 3
+FLOPS_PER_STEP = 170
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def run_gpu(prec, c_host, cfg, steps, warmup, resid_host):
+    import torch
+
+    import paper_2511_18511_amd as rtx
+
+    dev = torch.device("cuda", 0)
+    c = torch.from_numpy(c_host).to(dev)
+    resid = torch.from_numpy(resid_host).to(dev)
+    plan = rtx.Plan(cfg["nx"], cfg["ny"], cfg["h"], cfg["n_elem"], cfg["radius"], cfg["phi0"], prec=prec,
+                    integ=cfg["integ"], ds_px=cfg["ds_px"], tol_px=cfg["tol_px"], max_marches=cfg["max_marches"])
+    n = plan.n_all
+    out = plan.trace(c)  # allocates the output tensors once
+    grad = torch.zeros(cfg["ny"], cfg["nx"], dtype=plan.real, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * steps)]
+
+    def step(k=None):
+        plan.set_medium(c)
+        if k is not None:
+            ev[3 * k].record()
+        plan.trace(None, out=out)
+        if k is not None:
+            ev[3 * k + 1].record()
+        grad.zero_()
+        plan.adjoint(out["theta"], out["status"], resid, weight="length", grad=grad)
+        if k is not None:
+            ev[3 * k + 2].record()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    trace_ms = np.array([ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(steps)])
+    adj_ms = np.array([ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(steps)])
+    trace_steps, trace_rays, adj_steps = plan.stats()
+    st = out["status"].cpu().numpy()
+    res = {
+        "prec": prec,
+        "wall_s": wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "rays_per_s": n * steps / wall,
+        "trace_ms": float(np.median(trace_ms)),
+        "trace_ms_mean": float(trace_ms.mean()),
+        "adjoint_ms": float(np.median(adj_ms)),
+        "forward_rays_per_s": n / (float(trace_ms.mean()) * 1e-3),
+        "trace_rk_steps": int(trace_steps),
+        "trace_rays": int(trace_rays),
+        "adjoint_rk_steps": int(adj_steps),
+        "linked_fraction": float(np.mean(st == rtx.RTX_RAY_LINKED)),
+        "mean_marches": float(out["n_marches"].double().mean().item()),
+    }
+    plan.close()
+    return res, out
+
+
+def cpu_baseline(c, cfg, resid, max_seconds=30.0):
+    """The FP64 oracle on the host cores: linked trace + adjoint of the same
+    workload, pairs split over a thread pool (the oracle releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    threads = min(16, os.cpu_count() or 1)
+    ring = (cfg["n_elem"], cfg["radius"], cfg["phi0"])
+    pairs = synth.all_pairs(cfg["n_elem"])
+    med = oracle.grid_medium(c, cfg["h"])
+    # probe: time 2 x threads pairs, then size the sample to ~max_seconds/2
+    rng = np.random.default_rng(0)
+    order = rng.permutation(len(pairs))
+    t0 = time.perf_counter()
+    oracle.trace(med, ring, pairs[order[:64]])
+    per_pair = (time.perf_counter() - t0) / 64
+    n_sample = int(min(len(pairs), max(256, 0.5 * max_seconds * threads / max(per_pair, 1e-9))))
+    sub = np.sort(order[:n_sample])
+    chunks = np.array_split(sub, threads * 4)
+
+    def work(idx):
+        o = oracle.trace(med, ring, pairs[idx])
+        g = oracle.adjoint(c, cfg["h"], ring, pairs[idx], o["theta"], resid[idx], status=o["status"])
+        return g
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(work, chunks))
+    wall = time.perf_counter() - t0
+    full = n_sample == len(pairs)
+    return {"value": n_sample / wall, "unit": "linked rays/s", "cores": threads, "kind": "oracle",
+            "sample": ("all" if full else f"{n_sample} of {len(pairs)} seeded-uniform") +
+            f" pairs of the same workload, linked trace + adjoint, {wall:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path needs no cross-GPU exchange "
+              "for the forward pass, see DESIGN.md for how it shards", file=sys.stderr)
+        sys.exit(2)
+
+    cfg, c = synth.make_config(WORKLOAD)
+    n_pairs = cfg["n_elem"] * (cfg["n_elem"] - 1)
+    resid = synth.real_residual(n_pairs, cfg["resid_seed"], cfg["resid_std"])
+
+    f32, _ = run_gpu("f32c", c, cfg, args.steps, args.warmup, resid)
+    print(f"# f32c {f32['ms_per_step']:.3f} ms/step, trace {f32['trace_ms']:.3f} ms, adjoint "
+          f"{f32['adjoint_ms']:.3f} ms", file=sys.stderr, flush=True)
+    f64 = None
+    if not args.no_f64:
+        f64, _ = run_gpu("f64", c, cfg, args.steps, args.warmup, resid)
+        print(f"# f64 {f64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel (the linked trace), per launch
+    t_s = f32["trace_ms_mean"] * 1e-3
+    flops = f32["trace_rk_steps"] * FLOPS_PER_STEP
+    roof = {"bound": "alu", "achieved": flops / t_s / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": flops / t_s / 1e12 / PEAK_FP32_TFLOPS, "traffic": None}
+    gather = {"kernel": "k_trace<float>", "bytes_per_launch": f32["trace_rk_steps"] * GATHER_VALUES_PER_STEP * 4,
+              "achieved_GBs": f32["trace_rk_steps"] * GATHER_VALUES_PER_STEP * 4 / t_s / 1e9,
+              "vs_hbm_peak_frac": f32["trace_rk_steps"] * GATHER_VALUES_PER_STEP * 4 / t_s / 1e9 / PEAK_HBM_GBS}
+
+    cpu = None if args.no_cpu else cpu_baseline(c, cfg, resid)
+    line = {
+        "metric": "linked rays/s (ToF+path) and adjoint time; FP32-comp vs FP64 plain, same GPU",
+        "value": f32["rays_per_s"],
+        "unit": "linked rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256x256 grid at 0.5 mm, 12 seeded Gaussian inclusions on 1500 m/s, 256-element "
+                               "ring of radius 60 mm, all 65,280 ordered pairs, RK4 ds=0.25 px, linking tol 1e-3 px, "
+                               "cold straight-ray start, forward T+L then adjoint A^T r",
+                   "pairs": n_pairs, "grid": [cfg["ny"], cfg["nx"]], "ring_elements": cfg["n_elem"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "f32c": f32,
+        "f64": f64,
+        "f32c_over_f64": (f32["rays_per_s"] / f64["rays_per_s"]) if f64 else None,
+        "gather": gather,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

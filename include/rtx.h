@@ -1,0 +1,183 @@
+/*
+ * rtx.h -- C ABI of the MI355X (gfx950) library for two-point ray tracing of
+ * every emitter/receiver pair of a ring array through a gridded sound-speed map
+ * (arXiv 2511.18511: Sec. 3.2 ray tracing by the shooting method, Sec. 3.3
+ * bilinear grid-to-ray interpolation, Sec. 3.4 ray linking, Sec. 3.1 system
+ * matrix, Sec. 4.2 trapezoid accumulation along the ray, Appendix: the travel
+ * time obeys the Eikonal equation grad T . grad T = 1/c^2).
+ *
+ * Conventions shared by every call
+ *  - Grid: node (ix, iy) of an nx-by-ny grid with spacing h (metres) sits at
+ *    x = (ix - (nx-1)/2) h, y = (iy - (ny-1)/2) h.  Node arrays are row-major
+ *    [ny][nx] (index iy * nx + ix).  The ring is centred on the grid centre.
+ *  - Ring: element k sits at radius `radius` (metres) and angle
+ *    phi0 + 2 pi k / n_elem.  A pair is (emitter e, receiver r), e != r.  With
+ *    pairs == NULL every ordered pair is traced, pair i being
+ *    e = i / (n_elem - 1), k = i % (n_elem - 1), r = k < e ? k : k + 1.
+ *  - theta: launch angle of a pair's ray relative to the inward normal at the
+ *    emitter (radians, counter-clockwise positive, |theta| < pi/2).
+ *  - Ray march: arc-length steps of ds_px pixels of dx/ds = d,
+ *    dd/ds = -(G - (G.d) d) / c with G the per-pixel gradient of c, both taken
+ *    by bilinear interpolation of node values (the node gradient by second-order
+ *    central differences, second-order one-sided at the edges); classic RK4 or
+ *    Heun; d renormalised after every step.  The step that crosses the ring is cut
+ *    at the crossing (segment/circle intersection), giving a partial step ds'.
+ *  - Travel time T = h sum_m w_m / c(p_m) and length L = h ((M-1) ds + ds') with
+ *    trapezoid weights w_0 = ds/2, w_m = ds, w_{M-1} = (ds + ds')/2, w_M = ds'/2
+ *    over the step points p_0..p_M (p_M = interception point).
+ *  - Linking: misfit g = mod(phi_hit - phi_e, 2pi) - mod(phi_r - phi_e, 2pi),
+ *    miss_px = |g| radius / h.  Start from the straight-ray angle (or theta on
+ *    RTX_WARM_START), second point theta - g/2, then the secant through the two
+ *    latest rays that hit, safeguarded by the latest sign bracket of g, by the
+ *    angle limits +-(pi/2 - 1e-6) and by halving toward the last hitting angle
+ *    after a ray that never reached the ring.  Stops at miss_px <= tol_px
+ *    (LINKED) or after max_marches rays (NOT_CONVERGED, best ray returned).
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller unless
+ * marked (host).  Calls enqueue work on `stream` (a hipStream_t; NULL = the
+ * null stream) and return without waiting; outputs are valid once the stream
+ * reaches that point.  The library keeps no reference to caller memory after a
+ * call returns.  A plan owns device workspace (the packed medium) and must not
+ * be used by two streams at once.
+ *
+ * Errors: every call returns RTX_OK or a negative RTX_E_* code and then leaves a
+ * message for rtx_last_error() (per thread).  Host-detectable argument errors
+ * return RTX_E_ARG and enqueue nothing.  Per-ray problems never fail the call:
+ * they are reported in the int8 status of each pair (RTX_RAY_*): e == r or an
+ * element index out of range -> BAD_INPUT; a non-positive or NaN sound speed met
+ * at a ray point -> BAD_INPUT; no crossing within max_steps steps -> NO_HIT.
+ */
+#ifndef RTX_H
+#define RTX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rtx_plan_s *rtx_plan;
+
+enum rtx_status {
+    RTX_OK = 0,
+    RTX_E_ARG = -1,          /* invalid argument (nothing enqueued) */
+    RTX_E_HIP = -2,          /* a HIP runtime call or kernel launch failed */
+    RTX_E_NOMEM = -3,        /* device allocation failed */
+    RTX_E_UNSUPPORTED = -4,  /* option combination not implemented */
+    RTX_E_CAPACITY = -5      /* nnz_cap smaller than the number of weights */
+};
+enum rtx_precision {
+    RTX_F64 = 0,  /* every step in FP64 */
+    RTX_F32C = 1  /* FP32 march with compensated (2Sum) position, direction and
+                     travel-time accumulation; FP64 interception, misfit and
+                     secant update */
+};
+enum rtx_integrator { RTX_HEUN = 2, RTX_RK4 = 4 };
+enum rtx_flags {
+    RTX_WARM_START = 1u,  /* start linking from the given theta */
+    RTX_FIXED_ANGLE = 2u  /* trace once at the given theta, no linking */
+};
+enum rtx_weight { RTX_W_LENGTH = 0, RTX_W_DTDC = 1 };
+enum rtx_resid_kind { RTX_RESID_REAL = 0, RTX_RESID_RAYBORN_C64 = 1 };
+enum rtx_ray_status {
+    RTX_RAY_LINKED = 0,         /* miss <= tol (FIXED_ANGLE: the ray hit the ring) */
+    RTX_RAY_NOT_CONVERGED = 1,  /* max_marches rays, best one returned */
+    RTX_RAY_NO_HIT = 2,         /* no traced ray reached the ring */
+    RTX_RAY_BAD_INPUT = 3       /* bad pair or bad sound speed on the path */
+};
+
+typedef struct {
+    int32_t nx, ny; /* nodes; both >= 4 */
+    double h;       /* node spacing, metres, > 0 */
+} rtx_grid;
+
+typedef struct {
+    int32_t n_elem; /* >= 2 */
+    double radius;  /* metres; radius/h + max(1, ds_px) <= (min(nx,ny) - 1)/2 */
+    double phi0;    /* angle of element 0, radians */
+} rtx_ring;
+
+typedef struct {
+    int32_t prec;        /* rtx_precision */
+    int32_t integ;       /* rtx_integrator */
+    double ds_px;        /* step in pixels, 0 < ds_px <= 2 */
+    double tol_px;       /* linking tolerance on the miss, pixels, >= 0 */
+    int32_t max_marches; /* traced rays per pair, >= 1 (30 is the usual value) */
+    int32_t max_steps;   /* steps per ray; 0 = ceil(8 radius / (h ds_px)) */
+    uint32_t flags;      /* rtx_flags */
+} rtx_opts;
+
+/* Creates a plan: validates grid/ring/opts and allocates device workspace for
+   the packed medium (12 coefficients per grid cell in the plan's precision) and
+   for up to max_pairs pairs per call.  *out receives the plan (host object). */
+int rtx_plan_create(rtx_plan *out, const rtx_grid *grid, const rtx_ring *ring, const rtx_opts *opts,
+                    int64_t max_pairs);
+
+/* Frees the plan's device memory (synchronises the device first). */
+int rtx_plan_destroy(rtx_plan plan);
+
+/* Changes the per-call options (precision must not change). */
+int rtx_plan_set_opts(rtx_plan plan, const rtx_opts *opts);
+
+/* Packs the medium: c (device, float64 [ny][nx], m/s) -> node gradient and
+   per-cell bilinear coefficients of (c, dc/dx, dc/dy) in the plan's precision.
+   Later calls may pass c == NULL to reuse it. */
+int rtx_set_medium(rtx_plan plan, const double *c, void *stream);
+
+/* Linked ray tracing of n_pairs pairs (Sec. 3.2, 3.4): for each pair
+     theta     [n] in/out: start (RTX_WARM_START) or fixed angle (RTX_FIXED_ANGLE)
+                    on input; the linked (or best) launch angle on output;
+     tof       [n] travel time, seconds       (may be NULL)
+     len       [n] path length, metres        (may be NULL)
+     miss_px   [n] final miss, pixels         (may be NULL)
+     n_marches [n] rays traced                (may be NULL)
+     status    [n] rtx_ray_status             (required)
+   c: float64 [ny][nx] sound speed, or NULL for the medium of rtx_set_medium.
+   pairs: int32 [n][2] (emitter, receiver) or NULL for all ordered pairs.
+   Path weights (Sec. 3.1): when w_rowptr != NULL the rows
+   W_ij = h sum_m w_m phi_j(p_m) of the linked rays are emitted as CSR: with
+   w_col == NULL only w_rowptr [n+1] is written (count pass); otherwise w_col
+   (int32 node index iy*nx+ix, ascending, unique per row) and w_val (float or
+   double per precision, metres) are filled for nnz <= nnz_cap, else
+   RTX_E_CAPACITY.  Rows of pairs whose status is NO_HIT or BAD_INPUT are
+   empty.  The weights pass synchronises `stream` before returning. */
+int rtx_trace_rays(rtx_plan plan, const double *c, const int32_t *pairs, int64_t n_pairs, double *theta,
+                   double *tof, double *len, double *miss_px, int32_t *n_marches, int8_t *status,
+                   int64_t *w_rowptr, int32_t *w_col, void *w_val, int64_t nnz_cap, void *stream);
+
+/* Forward travel time only (the operator of the ToF inversion, Sec. 3.1):
+   same as rtx_trace_rays with len, miss, n_marches and weights omitted. */
+int rtx_tof_forward(rtx_plan plan, const double *c, const int32_t *pairs, int64_t n_pairs, double *theta,
+                    double *tof, int8_t *status, void *stream);
+
+/* Adjoint of the path weights along the rays traced at the given theta:
+     grad_j += sum_i rho_i sum_m w_m h kappa_m phi_j(p_m)
+   kappa = 1 (RTX_W_LENGTH: transpose of the system matrix) or
+   kappa = -1/c(p_m)^2 (RTX_W_DTDC: frozen-path derivative of T with respect to
+   the node sound speeds, i.e. the travel-time gradient).
+   rho = resid (RTX_RESID_REAL: float64 [n]) or, for RTX_RESID_RAYBORN_C64,
+   rho_i = sum_k w_k Im(exp(-i w_k T_i) r_ik) with w_k = 2 pi freqs_hz[k]
+   (freqs_hz host [n_freq]), r complex64 [n][n_freq] interleaved (re, im) and
+   T = tof (float64 [n], required for this kind): the adjoint of phase-only data
+   exp(i w T).  status (required, int8 [n], as returned by the forward call)
+   selects the pairs used: those whose status is LINKED or NOT_CONVERGED, i.e.
+   whose theta is a traced ray that reached the ring; others are skipped.  grad: [ny][nx] float (RTX_F32C) or double
+   (RTX_F64), accumulated into (the caller zeroes it).  Accumulation uses
+   atomics, so the FP32 result depends on summation order at rounding level. */
+int rtx_tof_adjoint(rtx_plan plan, const double *c, const int32_t *pairs, int64_t n_pairs,
+                    const double *theta, const int8_t *status, const double *tof, const void *resid,
+                    int32_t resid_kind, const double *freqs_hz, int32_t n_freq, int32_t weight, void *grad,
+                    void *stream);
+
+/* Work counters of the last trace / adjoint call on this plan (synchronises the
+   device): total RK steps marched and rays traced. */
+int rtx_plan_stats(rtx_plan plan, int64_t *trace_steps, int64_t *trace_rays, int64_t *adjoint_steps);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *rtx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTX_H */

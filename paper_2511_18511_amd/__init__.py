@@ -1,0 +1,178 @@
+"""MI355X-native linked ray tracing for ring-array ultrasound tomography.
+
+Two-point (shooting) ray tracing of every emitter/receiver pair through a gridded
+sound-speed map, with ray linking on the launch angle, travel time, path length
+and the adjoint of the path weights (arXiv 2511.18511, Sec. 3.1-3.4).  All
+computation runs in the HIP kernels of ``librtx.so``; this package only moves
+torch tensors (device memory) and the current stream across the C ABI.
+"""
+import ctypes as C
+
+import torch
+
+from . import _binding as B
+from ._binding import (  # noqa: F401
+    RTX_F32C, RTX_F64, RTX_HEUN, RTX_RK4, RTX_RAY_BAD_INPUT, RTX_RAY_LINKED, RTX_RAY_NO_HIT,
+    RTX_RAY_NOT_CONVERGED, RTX_W_DTDC, RTX_W_LENGTH, RtxError,
+)
+
+PRECISIONS = {"f64": B.RTX_F64, "f32c": B.RTX_F32C}
+INTEGRATORS = {"heun": B.RTX_HEUN, "rk4": B.RTX_RK4}
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_check(t, dtype, shape=None, name="tensor"):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA(HIP) tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Plan:
+    """Geometry + options + device workspace (the packed medium).
+
+    Lengths are metres; ``ds_px``/``tol_px`` are in grid pixels."""
+
+    def __init__(self, nx, ny, h, n_elem, radius, phi0=0.0, prec="f32c", integ="rk4", ds_px=0.25, tol_px=1e-3,
+                 max_marches=30, max_steps=0, max_pairs=None):
+        self.nx, self.ny, self.h = int(nx), int(ny), float(h)
+        self.n_elem, self.radius, self.phi0 = int(n_elem), float(radius), float(phi0)
+        self.prec = prec
+        self.real = torch.float32 if prec == "f32c" else torch.float64
+        self.n_all = self.n_elem * (self.n_elem - 1)
+        self.max_pairs = int(max_pairs or self.n_all)
+        self._opts = dict(integ=integ, ds_px=ds_px, tol_px=tol_px, max_marches=max_marches, max_steps=max_steps)
+        self._grid = B.rtx_grid(self.nx, self.ny, self.h)
+        self._ring = B.rtx_ring(self.n_elem, self.radius, self.phi0)
+        self._handle = B.rtx_plan_create(self._grid, self._ring, self._make_opts(0), self.max_pairs)
+
+    def _make_opts(self, flags, **over):
+        o = dict(self._opts, **over)
+        return B.rtx_opts(PRECISIONS[self.prec], INTEGRATORS[o["integ"]], float(o["ds_px"]), float(o["tol_px"]),
+                          int(o["max_marches"]), int(o["max_steps"]), int(flags))
+
+    def _apply(self, flags, **over):
+        B.rtx_plan_set_opts(self._handle, self._make_opts(flags, **over))
+
+    def close(self):
+        if getattr(self, "_handle", None):
+            B.rtx_plan_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def set_medium(self, c):
+        """Packs c (float64 [ny, nx] on the device) for later calls with c=None."""
+        _dev_check(c, torch.float64, (self.ny, self.nx), "c")
+        B.rtx_set_medium(self._handle, _ptr(c), _stream())
+
+    def _pairs(self, pairs):
+        if pairs is None:
+            return None, self.n_all
+        _dev_check(pairs, torch.int32, None, "pairs")
+        return pairs, pairs.shape[0]
+
+    def trace(self, c=None, pairs=None, theta=None, warm=False, fixed=False, out=None, **over):
+        """Linked (or fixed-angle) tracing.  Returns a dict of device tensors:
+        theta, tof (s), len (m), miss_px, n_marches, status."""
+        if c is not None:
+            _dev_check(c, torch.float64, (self.ny, self.nx), "c")
+        pairs, n = self._pairs(pairs)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if out is None:
+            out = {
+                "theta": torch.zeros(n, dtype=torch.float64, device=dev),
+                "tof": torch.empty(n, dtype=torch.float64, device=dev),
+                "len": torch.empty(n, dtype=torch.float64, device=dev),
+                "miss_px": torch.empty(n, dtype=torch.float64, device=dev),
+                "n_marches": torch.empty(n, dtype=torch.int32, device=dev),
+                "status": torch.empty(n, dtype=torch.int8, device=dev),
+            }
+        if theta is not None:
+            out["theta"].copy_(theta)
+        flags = (B.RTX_WARM_START if warm else 0) | (B.RTX_FIXED_ANGLE if fixed else 0)
+        self._apply(flags, **over)
+        B.rtx_trace_rays(self._handle, _ptr(c), _ptr(pairs), n, _ptr(out["theta"]), _ptr(out.get("tof")),
+                         _ptr(out.get("len")), _ptr(out.get("miss_px")), _ptr(out.get("n_marches")),
+                         _ptr(out["status"]), None, None, None, 0, _stream())
+        return out
+
+    def adjoint(self, theta, status, resid, weight="length", c=None, pairs=None, tof=None, freqs_hz=None,
+                grad=None, **over):
+        """grad[ny, nx] += sum_i rho_i sum_m w_m h kappa_m phi_j(p_m) along the rays
+        at the given angles (kappa = 1 for "length", -1/c^2 for "dtdc").  resid is
+        float64 [n] (rho) or complex64 [n, n_freq] with freqs_hz (ray-Born-style
+        phase data, needs tof)."""
+        pairs, n = self._pairs(pairs)
+        _dev_check(theta, torch.float64, (n,), "theta")
+        _dev_check(status, torch.int8, (n,), "status")
+        if grad is None:
+            grad = torch.zeros(self.ny, self.nx, dtype=self.real, device=theta.device)
+        _dev_check(grad, self.real, (self.ny, self.nx), "grad")
+        if resid.dtype == torch.complex64:
+            if tof is None or freqs_hz is None:
+                raise ValueError("complex residuals need tof and freqs_hz")
+            _dev_check(resid, torch.complex64, (n, len(freqs_hz)), "resid")
+            kind, nf = B.RTX_RESID_RAYBORN_C64, len(freqs_hz)
+        else:
+            _dev_check(resid, torch.float64, (n,), "resid")
+            kind, nf = B.RTX_RESID_REAL, 0
+        self._apply(0, **over)
+        wcode = {"length": B.RTX_W_LENGTH, "dtdc": B.RTX_W_DTDC}[weight]
+        B.rtx_tof_adjoint(self._handle, _ptr(c), _ptr(pairs), n, _ptr(theta), _ptr(status), _ptr(tof), _ptr(resid),
+                          kind, freqs_hz, nf, wcode, _ptr(grad), _stream())
+        return grad
+
+    def stats(self):
+        """(trace steps, trace rays, adjoint steps) of the last calls."""
+        return B.rtx_plan_stats(self._handle)
+
+
+def trace_rays(c, h, n_elem, radius, phi0=0.0, pairs=None, theta=None, warm=False, fixed=False, **opts):
+    """One-shot linked tracing of a float64 [ny, nx] device medium."""
+    ny, nx = c.shape
+    plan = Plan(nx, ny, h, n_elem, radius, phi0, **opts)
+    try:
+        return plan.trace(c, pairs=pairs, theta=theta, warm=warm, fixed=fixed)
+    finally:
+        torch.cuda.current_stream().synchronize()
+        plan.close()
+
+
+class ToF(torch.autograd.Function):
+    """T = ToF(c): linked travel times of all pairs of ``plan`` through c.
+
+    forward: linked tracing, warm-started from ``state["theta"]`` when present
+    (the linked angles are stored back into ``state``); backward: the
+    frozen-path travel-time gradient dT/dc (adjoint with kappa = -1/c^2)."""
+
+    @staticmethod
+    def forward(ctx, c, plan, state=None, pairs=None):
+        warm = state is not None and state.get("theta") is not None
+        out = plan.trace(c, pairs=pairs, theta=state["theta"] if warm else None, warm=warm)
+        if state is not None:
+            state["theta"] = out["theta"]
+            state["status"] = out["status"]
+        ctx.plan, ctx.pairs = plan, pairs
+        ctx.save_for_backward(c, out["theta"], out["status"])
+        return out["tof"]
+
+    @staticmethod
+    def backward(ctx, grad_t):
+        c, theta, status = ctx.saved_tensors
+        g = ctx.plan.adjoint(theta, status, grad_t.contiguous().to(torch.float64), weight="dtdc", c=c,
+                             pairs=ctx.pairs)
+        return g.to(c.dtype), None, None, None
+

@@ -1,0 +1,116 @@
+"""ctypes binding of librtx.so (argument marshalling only; every step of the
+computation runs in the HIP kernels of the library).  The names mirror the C
+ABI declared in include/rtx.h."""
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtx.so")
+
+RTX_OK, RTX_E_ARG, RTX_E_HIP, RTX_E_NOMEM, RTX_E_UNSUPPORTED, RTX_E_CAPACITY = 0, -1, -2, -3, -4, -5
+RTX_F64, RTX_F32C = 0, 1
+RTX_HEUN, RTX_RK4 = 2, 4
+RTX_WARM_START, RTX_FIXED_ANGLE = 1, 2
+RTX_W_LENGTH, RTX_W_DTDC = 0, 1
+RTX_RESID_REAL, RTX_RESID_RAYBORN_C64 = 0, 1
+RTX_RAY_LINKED, RTX_RAY_NOT_CONVERGED, RTX_RAY_NO_HIT, RTX_RAY_BAD_INPUT = 0, 1, 2, 3
+
+# every symbol include/rtx.h declares
+EXPORTS = ("rtx_plan_create", "rtx_plan_destroy", "rtx_plan_set_opts", "rtx_set_medium", "rtx_trace_rays",
+           "rtx_tof_forward", "rtx_tof_adjoint", "rtx_plan_stats", "rtx_last_error")
+
+
+class rtx_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("h", C.c_double)]
+
+
+class rtx_ring(C.Structure):
+    _fields_ = [("n_elem", C.c_int32), ("radius", C.c_double), ("phi0", C.c_double)]
+
+
+class rtx_opts(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("integ", C.c_int32), ("ds_px", C.c_double), ("tol_px", C.c_double),
+                ("max_marches", C.c_int32), ("max_steps", C.c_int32), ("flags", C.c_uint32)]
+
+
+class RtxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rtx error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Loads librtx.so; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                          "g.build()'` (hipcc, gfx950); there is no fallback path")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+    L.rtx_plan_create.argtypes = [C.POINTER(vp), C.POINTER(rtx_grid), C.POINTER(rtx_ring), C.POINTER(rtx_opts), i64]
+    L.rtx_plan_destroy.argtypes = [vp]
+    L.rtx_plan_set_opts.argtypes = [vp, C.POINTER(rtx_opts)]
+    L.rtx_set_medium.argtypes = [vp, vp, vp]
+    L.rtx_trace_rays.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+    L.rtx_tof_forward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+    L.rtx_tof_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(C.c_double), i32, i32, vp, vp]
+    L.rtx_plan_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.rtx_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        getattr(L, name).restype = C.c_char_p if name == "rtx_last_error" else C.c_int
+    _lib = L
+    return L
+
+
+def check(code):
+    if code != RTX_OK:
+        raise RtxError(code, load().rtx_last_error().decode())
+    return code
+
+
+def rtx_plan_create(grid, ring, opts, max_pairs):
+    h = C.c_void_p()
+    check(load().rtx_plan_create(C.byref(h), C.byref(grid), C.byref(ring), C.byref(opts), int(max_pairs)))
+    return h
+
+
+def rtx_plan_destroy(plan):
+    return check(load().rtx_plan_destroy(plan))
+
+
+def rtx_plan_set_opts(plan, opts):
+    return check(load().rtx_plan_set_opts(plan, C.byref(opts)))
+
+
+def rtx_set_medium(plan, c, stream):
+    return check(load().rtx_set_medium(plan, c, stream))
+
+
+def rtx_trace_rays(plan, c, pairs, n_pairs, theta, tof, len_, miss_px, n_marches, status, w_rowptr, w_col, w_val,
+                   nnz_cap, stream):
+    return check(load().rtx_trace_rays(plan, c, pairs, int(n_pairs), theta, tof, len_, miss_px, n_marches, status,
+                                       w_rowptr, w_col, w_val, int(nnz_cap), stream))
+
+
+def rtx_tof_forward(plan, c, pairs, n_pairs, theta, tof, status, stream):
+    return check(load().rtx_tof_forward(plan, c, pairs, int(n_pairs), theta, tof, status, stream))
+
+
+def rtx_tof_adjoint(plan, c, pairs, n_pairs, theta, status, tof, resid, resid_kind, freqs_hz, n_freq, weight, grad,
+                    stream):
+    fr = None
+    if freqs_hz is not None:
+        fr = (C.c_double * len(freqs_hz))(*[float(f) for f in freqs_hz])
+    return check(load().rtx_tof_adjoint(plan, c, pairs, int(n_pairs), theta, status, tof, resid, int(resid_kind), fr,
+                                        int(n_freq), int(weight), grad, stream))
+
+
+def rtx_plan_stats(plan):
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    check(load().rtx_plan_stats(plan, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value

@@ -1,0 +1,1053 @@
+// rtx.hip -- gfx950 (MI355X) kernels and C ABI for linked two-point ray tracing
+// of every emitter/receiver pair of a ring array through a gridded sound-speed
+// map (arXiv 2511.18511, Sec. 3.2-3.4), with travel time, path length, path
+// weights (Sec. 3.1) and their adjoint.  The C ABI is declared in include/rtx.h.
+//
+// Design (one GPU, HIP only):
+//  * The medium is packed once per call into per-cell bilinear coefficients
+//    (a, b, c, d) of f = a + b t + c s + d t s for f in (c, dc/dx, dc/dy): 12
+//    values per cell, so one interpolation is three 16-byte loads in FP32 (six
+//    in FP64) and nine FMAs.  Tables of up to 512x512 cells stay L2/MALL
+//    resident; rays gather from them at random, nothing streams from HBM.
+//  * One lane owns one pair.  The lane runs a flat loop whose body is exactly one
+//    integration step; when its ray reaches the ring the lane does the (rare,
+//    divergent) interception + misfit + secant update in FP64 and starts its next
+//    ray or its next pair in the same loop, so a wave never waits for its
+//    slowest ray between marches.  Pairs are dealt to lanes with a fixed stride.
+//  * FP32-compensated precision: positions (grid coordinates), directions and
+//    the travel-time sum are (hi, lo) float pairs updated with error-free
+//    2Sum; the direction is renormalised through an exact |d|^2 - 1 (Dekker
+//    products).  The interception, misfit, secant update and final T/L are FP64.
+//  * The adjoint re-marches each pair at its fixed angle and scatters its
+//    trapezoid-weighted hat contributions with hardware float atomics.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "rtx.h"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 2.0 * kPi;
+constexpr int kBlock = 256;
+constexpr int kCoef = 12;  // (c, gx, gy) x (a, b, c, d)
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(RTX_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ packing --
+// Node gradient in index units: second-order central differences, second-order
+// one-sided at the grid edges.
+__device__ inline double node_dx(const double *c, int nx, int ix, int iy)
+{
+    const double *r = c + (size_t)iy * nx;
+    if (ix == 0) return (-3.0 * r[0] + 4.0 * r[1] - r[2]) * 0.5;
+    if (ix == nx - 1) return (3.0 * r[nx - 1] - 4.0 * r[nx - 2] + r[nx - 3]) * 0.5;
+    return (r[ix + 1] - r[ix - 1]) * 0.5;
+}
+
+__device__ inline double node_dy(const double *c, int nx, int ny, int ix, int iy)
+{
+    const double *col = c + ix;
+    if (iy == 0) return (-3.0 * col[0] + 4.0 * col[(size_t)nx] - col[2 * (size_t)nx]) * 0.5;
+    if (iy == ny - 1)
+        return (3.0 * col[(size_t)(ny - 1) * nx] - 4.0 * col[(size_t)(ny - 2) * nx] + col[(size_t)(ny - 3) * nx]) *
+               0.5;
+    return (col[(size_t)(iy + 1) * nx] - col[(size_t)(iy - 1) * nx]) * 0.5;
+}
+
+// One thread per cell (ix, iy), ix < nx-1, iy < ny-1: coefficients of
+// f(t, s) = f00 + (f10 - f00) t + (f01 - f00) s + (f11 - f10 - f01 + f00) t s.
+template <class R>
+__global__ void k_pack(const double *__restrict__ c, int nx, int ny, R *__restrict__ tab)
+{
+    int ncx = nx - 1;
+    int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= (int64_t)ncx * (ny - 1)) return;
+    int ix = (int)(cell % ncx), iy = (int)(cell / ncx);
+    double f[3][4];
+    const int cx[4] = {ix, ix + 1, ix, ix + 1}, cy[4] = {iy, iy, iy + 1, iy + 1};
+    for (int k = 0; k < 4; k++) {
+        f[0][k] = c[(size_t)cy[k] * nx + cx[k]];
+        f[1][k] = node_dx(c, nx, cx[k], cy[k]);
+        f[2][k] = node_dy(c, nx, ny, cx[k], cy[k]);
+    }
+    R *o = tab + cell * kCoef;
+    for (int q = 0; q < 3; q++) {
+        o[4 * q + 0] = (R)f[q][0];
+        o[4 * q + 1] = (R)(f[q][1] - f[q][0]);
+        o[4 * q + 2] = (R)(f[q][2] - f[q][0]);
+        o[4 * q + 3] = (R)((f[q][3] - f[q][1]) - (f[q][2] - f[q][0]));
+    }
+}
+
+// -------------------------------------------------------------- arithmetic --
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float floor_(float x) { return floorf(x); }
+__device__ __forceinline__ double floor_(double x) { return floor(x); }
+__device__ __forceinline__ float fmin_(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double fmin_(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float fmax_(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double fmax_(double a, double b) { return fmax(a, b); }
+
+// Error-free sum (Knuth): a + b = s + e exactly.
+template <class R>
+__device__ __forceinline__ void two_sum(R a, R b, R &s, R &e)
+{
+    s = a + b;
+    R bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// ----------------------------------------------------------- medium lookup --
+template <class R>
+struct Medium {
+    const R *tab;
+    int nx, ny;
+};
+
+__device__ __forceinline__ void load_cell(const float *tab, int cell, float (&v)[12])
+{
+    const float4 *p = reinterpret_cast<const float4 *>(tab) + 3 * (size_t)cell;
+    float4 a = p[0], b = p[1], c = p[2];
+    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w;
+    v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+    v[8] = c.x, v[9] = c.y, v[10] = c.z, v[11] = c.w;
+}
+
+__device__ __forceinline__ void load_cell(const double *tab, int cell, double (&v)[12])
+{
+    const double2 *p = reinterpret_cast<const double2 *>(tab) + 6 * (size_t)cell;
+    for (int k = 0; k < 6; k++) {
+        double2 a = p[k];
+        v[2 * k] = a.x;
+        v[2 * k + 1] = a.y;
+    }
+}
+
+// Interpolation at grid coordinate (uh + du, vh + dv) (u = ix-space, v =
+// iy-space); du, dv are small offsets kept apart from the hi parts so that the
+// local coordinates t, s keep full precision.  Cell index clamped to the grid,
+// t and s to [0, 1].
+template <class R>
+struct Sample {
+    R c, gx, gy, t, s;
+    int ix, iy;
+};
+
+template <class R>
+__device__ __forceinline__ Sample<R> lookup(const Medium<R> &M, R uh, R du, R vh, R dv)
+{
+    Sample<R> o;
+    R fu = floor_(uh + du), fv = floor_(vh + dv);
+    fu = fmin_(fmax_(fu, (R)0), (R)(M.nx - 2));
+    fv = fmin_(fmax_(fv, (R)0), (R)(M.ny - 2));
+    R t = (uh - fu) + du, s = (vh - fv) + dv;
+    o.t = fmin_(fmax_(t, (R)0), (R)1);
+    o.s = fmin_(fmax_(s, (R)0), (R)1);
+    o.ix = (int)fu;
+    o.iy = (int)fv;
+    R v[12];
+    load_cell(M.tab, o.iy * (M.nx - 1) + o.ix, v);
+    o.c = fma(o.s, fma(o.t, v[3], v[2]), fma(o.t, v[1], v[0]));
+    o.gx = fma(o.s, fma(o.t, v[7], v[6]), fma(o.t, v[5], v[4]));
+    o.gy = fma(o.s, fma(o.t, v[11], v[10]), fma(o.t, v[9], v[8]));
+    return o;
+}
+
+// dd/ds = -(G - (G.d) d) / c
+template <class R>
+__device__ __forceinline__ void curvature(const Sample<R> &S, R ic, R dx, R dy, R &kx, R &ky)
+{
+    R gd = S.gx * dx + S.gy * dy;
+    kx = (gd * dx - S.gx) * ic;
+    ky = (gd * dy - S.gy) * ic;
+}
+
+// --------------------------------------------------------------- ray state --
+// Position (grid coordinates) and direction as hi + lo pairs; the lo parts stay
+// zero in FP64.
+template <class R>
+struct Ray {
+    R uh, ul, vh, vl;
+    R dxh, dxl, dyh, dyl;
+    R Th, Tl;  // running trapezoid sum of w/c (pixels * s/m), compensated
+    int m;     // steps taken in this ray
+};
+
+template <class R, bool COMP>
+__device__ __forceinline__ void ray_start(Ray<R> &ray, double pu, double pv, double psi)
+{
+    double sp, cp;
+    sincos(psi, &sp, &cp);
+    ray.uh = (R)pu;
+    ray.vh = (R)pv;
+    ray.dxh = (R)cp;
+    ray.dyh = (R)sp;
+    if (COMP) {
+        ray.ul = (R)(pu - (double)ray.uh);
+        ray.vl = (R)(pv - (double)ray.vh);
+        ray.dxl = (R)(cp - (double)ray.dxh);
+        ray.dyl = (R)(sp - (double)ray.dyh);
+    } else {
+        ray.ul = ray.vl = ray.dxl = ray.dyl = (R)0;
+    }
+    ray.Th = ray.Tl = (R)0;
+    ray.m = 0;
+}
+
+// Result of one integration step: the new state is written to `nxt`; `s1` is
+// the medium at the step's start point p_m (its c gives the quadrature term).
+template <class R>
+struct StepOut {
+    Sample<R> s1;
+    R ic1;
+};
+
+template <class R, bool COMP, int INTEG>
+__device__ __forceinline__ StepOut<R> ray_step(const Medium<R> &M, const Ray<R> &y, Ray<R> &nxt, R ds)
+{
+    StepOut<R> o;
+    const R d1x = y.dxh + y.dxl, d1y = y.dyh + y.dyl;
+    o.s1 = lookup(M, y.uh, y.ul, y.vh, y.vl);
+    o.ic1 = rcp(o.s1.c);
+    R k1x, k1y;
+    curvature(o.s1, o.ic1, d1x, d1y, k1x, k1y);
+    R incx, incy, idx, idy;
+    if (INTEG == 4) {
+        const R h2 = ds * (R)0.5;
+        R d2x = fma(h2, k1x, d1x), d2y = fma(h2, k1y, d1y);
+        Sample<R> s2 = lookup(M, y.uh, fma(h2, d1x, y.ul), y.vh, fma(h2, d1y, y.vl));
+        R k2x, k2y;
+        curvature(s2, rcp(s2.c), d2x, d2y, k2x, k2y);
+        R d3x = fma(h2, k2x, d1x), d3y = fma(h2, k2y, d1y);
+        Sample<R> s3 = lookup(M, y.uh, fma(h2, d2x, y.ul), y.vh, fma(h2, d2y, y.vl));
+        R k3x, k3y;
+        curvature(s3, rcp(s3.c), d3x, d3y, k3x, k3y);
+        R d4x = fma(ds, k3x, d1x), d4y = fma(ds, k3y, d1y);
+        Sample<R> s4 = lookup(M, y.uh, fma(ds, d3x, y.ul), y.vh, fma(ds, d3y, y.vl));
+        R k4x, k4y;
+        curvature(s4, rcp(s4.c), d4x, d4y, k4x, k4y);
+        // x+ = x + ds/6 (d1 + 2 d2 + 2 d3 + d4) = x + ds d1 + ds^2/6 (k1 + k2 + k3)
+        const R c6 = ds * ds * (R)(1.0 / 6.0), s6 = ds * (R)(1.0 / 6.0);
+        incx = fma(c6, k1x + k2x + k3x, ds * d1x);
+        incy = fma(c6, k1y + k2y + k3y, ds * d1y);
+        idx = s6 * (k1x + (R)2 * (k2x + k3x) + k4x);
+        idy = s6 * (k1y + (R)2 * (k2y + k3y) + k4y);
+    } else {
+        R d2x = fma(ds, k1x, d1x), d2y = fma(ds, k1y, d1y);
+        Sample<R> s2 = lookup(M, y.uh, fma(ds, d1x, y.ul), y.vh, fma(ds, d1y, y.vl));
+        R k2x, k2y;
+        curvature(s2, rcp(s2.c), d2x, d2y, k2x, k2y);
+        // x+ = x + ds/2 (d1 + d2) = x + ds d1 + ds^2/2 k1
+        incx = fma(ds * ds * (R)0.5, k1x, ds * d1x);
+        incy = fma(ds * ds * (R)0.5, k1y, ds * d1y);
+        idx = ds * (R)0.5 * (k1x + k2x);
+        idy = ds * (R)0.5 * (k1y + k2y);
+    }
+    if (COMP) {
+        R s, e;
+        two_sum(y.uh, incx, s, e);
+        nxt.uh = s;
+        nxt.ul = y.ul + e;
+        two_sum(y.vh, incy, s, e);
+        nxt.vh = s;
+        nxt.vl = y.vl + e;
+        two_sum(y.dxh, idx, s, e);
+        R dxh = s, dxl = y.dxl + e;
+        two_sum(y.dyh, idy, s, e);
+        R dyh = s, dyl = y.dyl + e;
+        // renormalise: eta = |d|^2 - 1 from exact squares of the hi parts
+        R px = dxh * dxh, ex = fma(dxh, dxh, -px);
+        R py = dyh * dyh, ey = fma(dyh, dyh, -py);
+        R big = fmax_(px, py), sml = fmin_(px, py);
+        R eta = ((big - (R)1) + sml) + (ex + ey + (R)2 * (dxh * dxl + dyh * dyl));
+        R f = (R)-0.5 * eta;
+        nxt.dxh = dxh;
+        nxt.dyh = dyh;
+        nxt.dxl = fma(dxh, f, dxl);
+        nxt.dyl = fma(dyh, f, dyl);
+    } else {
+        nxt.uh = y.uh + incx;
+        nxt.vh = y.vh + incy;
+        nxt.ul = nxt.vl = (R)0;
+        R dx = y.dxh + idx, dy = y.dyh + idy;
+        R nrm = sqrt(dx * dx + dy * dy);
+        nxt.dxh = dx / nrm;
+        nxt.dyh = dy / nrm;
+        nxt.dxl = nxt.dyl = (R)0;
+    }
+    return o;
+}
+
+// Trapezoid term of step-start sample p_m when the step does not cross.
+template <class R, bool COMP>
+__device__ __forceinline__ void add_T(Ray<R> &y, R term)
+{
+    if (COMP) {
+        R s, e;
+        two_sum(y.Th, term, s, e);
+        y.Th = s;
+        y.Tl += e;
+    } else {
+        y.Th += term;
+    }
+}
+
+// ------------------------------------------------------------- geometry (FP64) --
+struct Geo {
+    int nx, ny, n_elem;
+    double cx, cy;  // grid coordinate of the ring centre
+    double R;       // ring radius, pixels
+    double phi0, h, ds;
+};
+
+__device__ __forceinline__ double elem_angle(const Geo &g, int k)
+{
+    return g.phi0 + 2.0 * kPi * k / g.n_elem;
+}
+
+__device__ __forceinline__ double mod2pi(double a)
+{
+    double r = fmod(a, kTwoPi);
+    if (r < 0) r += kTwoPi;
+    return r;
+}
+
+// Crossing of the last step: larger root t in (0, 1] of |p + t (q - p)|^2 = R^2.
+struct Hit {
+    double qx, qy, t;
+};
+
+template <class R>
+__device__ __forceinline__ Hit intersect(const Geo &g, const Ray<R> &a, const Ray<R> &b)
+{
+    double px = ((double)a.uh - g.cx) + (double)a.ul, py = ((double)a.vh - g.cy) + (double)a.vl;
+    double qx = ((double)b.uh - g.cx) + (double)b.ul, qy = ((double)b.vh - g.cy) + (double)b.vl;
+    double ax = qx - px, ay = qy - py;
+    double A = ax * ax + ay * ay, B = 2.0 * (px * ax + py * ay), C = px * px + py * py - g.R * g.R;
+    double D = fmax(B * B - 4.0 * A * C, 0.0);
+    double t = (B >= 0) ? (-2.0 * C) / (B + sqrt(D)) : (-B + sqrt(D)) / (2.0 * A);
+    t = fmin(fmax(t, 0.0), 1.0);
+    Hit h;
+    h.qx = px + t * ax;
+    h.qy = py + t * ay;
+    h.t = t;
+    return h;
+}
+
+// Medium at a ring-centred FP64 pixel point.
+template <class R, bool COMP>
+__device__ __forceinline__ Sample<R> lookup_at(const Medium<R> &M, const Geo &g, double px, double py)
+{
+    double u = px + g.cx, v = py + g.cy;
+    R uh = (R)u, vh = (R)v;
+    R ul = COMP ? (R)(u - (double)uh) : (R)0, vl = COMP ? (R)(v - (double)vh) : (R)0;
+    return lookup(M, uh, ul, vh, vl);
+}
+
+// ------------------------------------------------------------------ linking --
+struct Link {
+    double th, th0, tha, ga, thb, gb, th_neg, th_pos;
+    double best_miss, best_th, best_T, best_L;
+    int nvalid, have_neg, have_pos, n_marches;
+};
+
+__device__ __forceinline__ void link_reset(Link &L, double th0)
+{
+    L.th = L.th0 = th0;
+    L.tha = L.ga = L.thb = L.gb = L.th_neg = L.th_pos = 0.0;
+    L.best_miss = INFINITY;
+    L.best_th = th0;
+    L.best_T = L.best_L = NAN;
+    L.nvalid = L.have_neg = L.have_pos = L.n_marches = 0;
+}
+
+// Next launch angle after a ray that hit with misfit g (secant through the two
+// latest hitting rays, homogeneous Newton step for the second point,
+// safeguarded by the sign bracket or by the angle limits).
+__device__ __forceinline__ double link_next_hit(Link &L, double g)
+{
+    const double lim = kPi / 2.0 - 1e-6;
+    double th = L.th;
+    if (g < 0) {
+        L.have_neg = 1;
+        L.th_neg = th;
+    }
+    if (g > 0) {
+        L.have_pos = 1;
+        L.th_pos = th;
+    }
+    L.tha = L.thb;
+    L.ga = L.gb;
+    L.thb = th;
+    L.gb = g;
+    L.nvalid++;
+    bool den_zero = false;
+    double nx;
+    if (L.nvalid == 1) {
+        nx = th - g / 2.0;
+    } else if (L.gb - L.ga == 0.0) {
+        den_zero = true;
+        nx = th - g / 2.0;
+    } else {
+        nx = L.thb - L.gb * (L.thb - L.tha) / (L.gb - L.ga);
+    }
+    if (L.have_neg && L.have_pos) {
+        double lo = fmin(L.th_neg, L.th_pos), hi = fmax(L.th_neg, L.th_pos);
+        if (den_zero || !(nx > lo && nx < hi)) nx = 0.5 * (L.th_neg + L.th_pos);
+    } else {
+        if (!(nx < lim) && nx == nx) nx = 0.5 * (th + lim);
+        if (!(nx > -lim) && nx == nx) nx = 0.5 * (th - lim);
+        if (!(nx == nx)) nx = 0.5 * th;
+    }
+    return nx;
+}
+
+// ------------------------------------------------------------ trace kernel --
+struct TraceArgs {
+    const int32_t *pairs;
+    int64_t n_pairs;
+    double *theta, *tof, *len, *miss;
+    int32_t *n_marches;
+    int8_t *status;
+    int max_marches, max_steps;
+    double tol;
+    uint32_t flags;
+    unsigned long long *stats;  // [gridDim.x][2]: steps, rays
+};
+
+__device__ __forceinline__ bool pair_of(const TraceArgs &A, const Geo &g, int64_t p, int &e, int &r)
+{
+    if (A.pairs) {
+        e = A.pairs[2 * p];
+        r = A.pairs[2 * p + 1];
+    } else {
+        int64_t k = p % (g.n_elem - 1);
+        e = (int)(p / (g.n_elem - 1));
+        r = (int)(k < e ? k : k + 1);
+    }
+    return e != r && e >= 0 && r >= 0 && e < g.n_elem && r < g.n_elem;
+}
+
+__device__ __forceinline__ void write_pair(const TraceArgs &A, int64_t p, double th, double T, double Lm,
+                                           double miss, int nm, int st)
+{
+    if (!(A.flags & RTX_FIXED_ANGLE)) A.theta[p] = th;
+    if (A.tof) A.tof[p] = T;
+    if (A.len) A.len[p] = Lm;
+    if (A.miss) A.miss[p] = miss;
+    if (A.n_marches) A.n_marches[p] = nm;
+    A.status[p] = (int8_t)st;
+}
+
+template <class R, bool COMP>
+__device__ __forceinline__ void start_ray(Ray<R> &ray, const Geo &g, int e, double th)
+{
+    double pe = elem_angle(g, e);
+    double ex = g.R * cos(pe), ey = g.R * sin(pe);
+    ray_start<R, COMP>(ray, ex + g.cx, ey + g.cy, pe + kPi + th);
+}
+
+// Sum of per-lane counters over the block, written to out[blockIdx.x].
+__device__ void block_sum2(unsigned long long a, unsigned long long b, unsigned long long *out)
+{
+    __shared__ unsigned long long sa[kBlock / 64], sb[kBlock / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        sa[w] = a;
+        sb[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long ta = 0, tb = 0;
+        for (int k = 0; k < (int)(blockDim.x / 64); k++) {
+            ta += sa[k];
+            tb += sb[k];
+        }
+        out[2 * blockIdx.x] = ta;
+        out[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+template <class R, bool COMP, int INTEG>
+__global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs A)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool fixed = (A.flags & RTX_FIXED_ANGLE) != 0;
+    const R ds = (R)g.ds;
+    const R R2 = (R)(g.R * g.R);
+    const R cx = (R)g.cx, cy = (R)g.cy;
+    unsigned long long n_steps = 0, n_rays = 0;
+
+    Ray<R> ray;
+    Link L;
+    int e = 0, r = 0;
+    double pe = 0, dr = 0;  // emitter angle, receiver offset mod 2pi
+    bool active = false;
+
+    // Takes pairs from p onward until one is valid (invalid ones are written).
+    auto next_pair = [&]() {
+        while (p < A.n_pairs) {
+            if (pair_of(A, g, p, e, r)) {
+                pe = elem_angle(g, e);
+                dr = mod2pi(elem_angle(g, r) - pe);
+                double th0 = (A.flags & (RTX_WARM_START | RTX_FIXED_ANGLE)) ? A.theta[p] : (dr - kPi) / 2.0;
+                link_reset(L, th0);
+                start_ray<R, COMP>(ray, g, e, th0);
+                active = true;
+                return;
+            }
+            write_pair(A, p, A.theta[p], NAN, NAN, NAN, 0, RTX_RAY_BAD_INPUT);
+            p += stride;
+        }
+        active = false;
+    };
+    next_pair();
+
+    while (active) {
+        Ray<R> nxt;
+        StepOut<R> so = ray_step<R, COMP, INTEG>(M, ray, nxt, ds);
+        n_steps++;
+        const R w_start = ray.m == 0 ? ds * (R)0.5 : ds;
+        const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
+        R pu = (nxt.uh - cx) + nxt.ul, pv = (nxt.vh - cy) + nxt.vl;
+        const bool crossed = !bad && (pu * pu + pv * pv >= R2);
+        const bool exhausted = !bad && !crossed && (ray.m + 1 >= A.max_steps);
+        if (!(bad || crossed || exhausted)) {
+            add_T<R, COMP>(ray, w_start * so.ic1);
+            nxt.Th = ray.Th;
+            nxt.Tl = ray.Tl;
+            nxt.m = ray.m + 1;
+            ray = nxt;
+            continue;
+        }
+        // ---- end of one ray (rare, divergent) ----
+        n_rays++;
+        L.n_marches++;
+        int st = RTX_RAY_NO_HIT;
+        double g_mis = NAN, T = NAN, Lm = NAN;
+        if (bad) {
+            st = RTX_RAY_BAD_INPUT;
+        } else if (crossed) {
+            Hit hit = intersect<R>(g, ray, nxt);
+            double dsp = hit.t * g.ds;
+            Sample<R> sq = lookup_at<R, COMP>(M, g, hit.qx, hit.qy);
+            if (!(sq.c > (R)0)) {
+                st = RTX_RAY_BAD_INPUT;
+            } else {
+                double wm = ray.m == 0 ? 0.5 * dsp : 0.5 * (g.ds + dsp);
+                double acc = ((double)ray.Th + (double)ray.Tl) + wm * (double)so.ic1 +
+                             0.5 * dsp * (double)rcp(sq.c);
+                T = acc * g.h;
+                Lm = (ray.m * g.ds + dsp) * g.h;
+                g_mis = mod2pi(atan2(hit.qy, hit.qx) - pe) - dr;
+                st = RTX_RAY_LINKED;
+            }
+        }
+        bool pair_done = false;
+        if (fixed) {
+            write_pair(A, p, L.th, T, Lm, fabs(g_mis) * g.R, 1, st);
+            pair_done = true;
+        } else if (st == RTX_RAY_BAD_INPUT) {
+            write_pair(A, p, L.th0, NAN, NAN, NAN, L.n_marches, RTX_RAY_BAD_INPUT);
+            pair_done = true;
+        } else {
+            double th_next;
+            if (st == RTX_RAY_LINKED) {
+                double miss = fabs(g_mis) * g.R;
+                if (miss < L.best_miss) {
+                    L.best_miss = miss;
+                    L.best_th = L.th;
+                    L.best_T = T;
+                    L.best_L = Lm;
+                }
+                if (miss <= A.tol) {
+                    write_pair(A, p, L.th, T, Lm, miss, L.n_marches, RTX_RAY_LINKED);
+                    pair_done = true;
+                }
+                th_next = pair_done ? 0.0 : link_next_hit(L, g_mis);
+            } else {
+                th_next = L.nvalid > 0 ? 0.5 * (L.th + L.thb) : 0.5 * L.th;
+            }
+            if (!pair_done && L.n_marches >= A.max_marches) {
+                if (L.best_miss < INFINITY)
+                    write_pair(A, p, L.best_th, L.best_T, L.best_L, L.best_miss, L.n_marches,
+                               RTX_RAY_NOT_CONVERGED);
+                else
+                    write_pair(A, p, L.th0, NAN, NAN, NAN, L.n_marches, RTX_RAY_NO_HIT);
+                pair_done = true;
+            }
+            if (!pair_done) {
+                L.th = th_next;
+                start_ray<R, COMP>(ray, g, e, th_next);
+            }
+        }
+        if (pair_done) {
+            p += stride;
+            next_pair();
+        }
+    }
+    block_sum2(n_steps, n_rays, A.stats);
+}
+
+// ---------------------------------------------------------- adjoint kernel --
+struct AdjArgs {
+    const int32_t *pairs;
+    int64_t n_pairs;
+    const double *theta;
+    const int8_t *status;
+    const double *rho;
+    int weight;
+    int max_steps;
+    unsigned long long *stats;
+};
+
+template <class R>
+__device__ __forceinline__ void scatter4(R *grad, int nx, const Sample<R> &s, R a)
+{
+    R omt = (R)1 - s.t, oms = (R)1 - s.s;
+    size_t n0 = (size_t)s.iy * nx + s.ix;
+    unsafeAtomicAdd(grad + n0, a * omt * oms);
+    unsafeAtomicAdd(grad + n0 + 1, a * s.t * oms);
+    unsafeAtomicAdd(grad + n0 + nx, a * omt * s.s);
+    unsafeAtomicAdd(grad + n0 + nx + 1, a * s.t * s.s);
+}
+
+template <class R, bool COMP, int INTEG>
+__global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs A, R *__restrict__ grad)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const R ds = (R)g.ds;
+    const R R2 = (R)(g.R * g.R);
+    const R cx = (R)g.cx, cy = (R)g.cy;
+    unsigned long long n_steps = 0, n_rays = 0;
+    Ray<R> ray;
+    R scale = 0;  // rho h
+    bool active = false;
+    TraceArgs pa;
+    pa.pairs = A.pairs;
+
+    auto next_pair = [&]() {
+        while (p < A.n_pairs) {
+            int e, r;
+            bool ok = pair_of(pa, g, p, e, r);
+            ok = ok && (A.status[p] == RTX_RAY_LINKED || A.status[p] == RTX_RAY_NOT_CONVERGED);
+            double rho = ok ? A.rho[p] : 0.0;
+            if (ok && rho != 0.0) {
+                start_ray<R, COMP>(ray, g, e, A.theta[p]);
+                scale = (R)(rho * g.h);
+                active = true;
+                return;
+            }
+            p += stride;
+        }
+        active = false;
+    };
+    next_pair();
+
+    while (active) {
+        Ray<R> nxt;
+        StepOut<R> so = ray_step<R, COMP, INTEG>(M, ray, nxt, ds);
+        n_steps++;
+        const R kap = A.weight == RTX_W_DTDC ? -so.ic1 * so.ic1 : (R)1;
+        const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
+        R pu = (nxt.uh - cx) + nxt.ul, pv = (nxt.vh - cy) + nxt.vl;
+        const bool crossed = !bad && (pu * pu + pv * pv >= R2);
+        const bool exhausted = !bad && !crossed && (ray.m + 1 >= A.max_steps);
+        if (!(bad || crossed || exhausted)) {
+            const R w = ray.m == 0 ? ds * (R)0.5 : ds;
+            scatter4(grad, M.nx, so.s1, scale * w * kap);
+            nxt.m = ray.m + 1;
+            ray = nxt;
+            continue;
+        }
+        n_rays++;
+        if (crossed) {
+            Hit hit = intersect<R>(g, ray, nxt);
+            double dsp = hit.t * g.ds;
+            Sample<R> sq = lookup_at<R, COMP>(M, g, hit.qx, hit.qy);
+            if (sq.c > (R)0) {
+                R wm = (R)(ray.m == 0 ? 0.5 * dsp : 0.5 * (g.ds + dsp));
+                scatter4(grad, M.nx, so.s1, scale * wm * kap);
+                R icq = rcp(sq.c);
+                R kq = A.weight == RTX_W_DTDC ? -icq * icq : (R)1;
+                scatter4(grad, M.nx, sq, scale * (R)(0.5 * dsp) * kq);
+            }
+        }
+        p += stride;
+        next_pair();
+    }
+    block_sum2(n_steps, n_rays, A.stats);
+}
+
+// Per pair: rho_i = sum_k w_k Im(exp(-i w_k T_i) r_ik), one wave per pair, lanes
+// over frequencies (coalesced 8-byte complex64 loads), phase reduced in FP64.
+__global__ void __launch_bounds__(kBlock) k_rayborn_rho(int64_t n, int n_freq, const double *__restrict__ T,
+                                                         const double *__restrict__ omega,
+                                                         const float2 *__restrict__ resid, double *__restrict__ rho)
+{
+    int lane = threadIdx.x & 63;
+    int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= n) return;
+    double Ti = T[i], acc = 0.0;
+    for (int k = lane; k < n_freq; k += 64) {
+        double w = omega[k];
+        double ph = fmod(w * Ti, kTwoPi);
+        double sp, cp;
+        sincos(ph, &sp, &cp);
+        float2 rr = resid[i * n_freq + k];
+        acc += w * ((double)rr.y * cp - (double)rr.x * sp);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) rho[i] = acc;
+}
+
+}  // namespace
+
+// ===================================================================== plan ==
+struct rtx_plan_s {
+    rtx_grid grid;
+    rtx_ring ring;
+    rtx_opts opts;
+    int64_t max_pairs;
+    void *tab = nullptr;  // packed medium
+    bool have_medium = false;
+    unsigned long long *stats = nullptr;  // [kMaxBlocks][2] trace, then adjoint
+    int stat_blocks_trace = 0, stat_blocks_adj = 0;
+    double *rho = nullptr;     // [max_pairs] ray-Born reduction
+    double *omega = nullptr;   // [n_freq_cap]
+    int n_freq_cap = 0;
+    int n_cu = 0;
+};
+
+namespace {
+
+constexpr int kMaxBlocks = 8192;
+
+int check_opts(const rtx_grid *g, const rtx_ring *r, const rtx_opts *o)
+{
+    if (!g || !r || !o) return fail(RTX_E_ARG, "null grid/ring/opts");
+    if (g->nx < 4 || g->ny < 4) return fail(RTX_E_ARG, "grid must be at least 4x4 (got %dx%d)", g->nx, g->ny);
+    if (!(g->h > 0)) return fail(RTX_E_ARG, "grid spacing h must be > 0");
+    if (r->n_elem < 2) return fail(RTX_E_ARG, "ring needs >= 2 elements");
+    if (!(r->radius > 0)) return fail(RTX_E_ARG, "ring radius must be > 0");
+    if (o->prec != RTX_F64 && o->prec != RTX_F32C) return fail(RTX_E_ARG, "unknown precision %d", o->prec);
+    if (o->integ != RTX_HEUN && o->integ != RTX_RK4) return fail(RTX_E_ARG, "unknown integrator %d", o->integ);
+    if (!(o->ds_px > 0 && o->ds_px <= 2)) return fail(RTX_E_ARG, "ds_px must be in (0, 2]");
+    if (!(o->tol_px >= 0)) return fail(RTX_E_ARG, "tol_px must be >= 0");
+    if (o->max_marches < 1) return fail(RTX_E_ARG, "max_marches must be >= 1");
+    if (o->max_steps < 0) return fail(RTX_E_ARG, "max_steps must be >= 0");
+    double rpx = r->radius / g->h;
+    double half = 0.5 * (std::min(g->nx, g->ny) - 1);
+    if (rpx + std::max(1.0, o->ds_px) > half)
+        return fail(RTX_E_ARG, "ring (radius %.3f px) does not fit the grid with a margin of max(1, ds) px", rpx);
+    return RTX_OK;
+}
+
+Geo make_geo(const rtx_plan_s *P)
+{
+    Geo g;
+    g.nx = P->grid.nx;
+    g.ny = P->grid.ny;
+    g.n_elem = P->ring.n_elem;
+    g.cx = 0.5 * (P->grid.nx - 1);
+    g.cy = 0.5 * (P->grid.ny - 1);
+    g.R = P->ring.radius / P->grid.h;
+    g.phi0 = P->ring.phi0;
+    g.h = P->grid.h;
+    g.ds = P->opts.ds_px;
+    return g;
+}
+
+int max_steps_of(const rtx_plan_s *P)
+{
+    if (P->opts.max_steps > 0) return P->opts.max_steps;
+    return (int)ceil(8.0 * (P->ring.radius / P->grid.h) / P->opts.ds_px);
+}
+
+int pack(rtx_plan_s *P, const double *c, hipStream_t s)
+{
+    if (!c) {
+        if (!P->have_medium) return fail(RTX_E_ARG, "c is NULL and no medium was set");
+        return RTX_OK;
+    }
+    int64_t cells = (int64_t)(P->grid.nx - 1) * (P->grid.ny - 1);
+    int blocks = (int)((cells + kBlock - 1) / kBlock);
+    if (P->opts.prec == RTX_F32C)
+        hipLaunchKernelGGL(k_pack<float>, dim3(blocks), dim3(kBlock), 0, s, c, P->grid.nx, P->grid.ny,
+                           (float *)P->tab);
+    else
+        hipLaunchKernelGGL(k_pack<double>, dim3(blocks), dim3(kBlock), 0, s, c, P->grid.nx, P->grid.ny,
+                           (double *)P->tab);
+    HIP_TRY(hipGetLastError());
+    P->have_medium = true;
+    return RTX_OK;
+}
+
+// Persistent launch: no more blocks than can be resident at once (lanes take
+// further pairs with a fixed stride), and no more than the pairs need.
+template <class K>
+int grid_blocks(const rtx_plan_s *P, K kernel, int64_t n)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int64_t want = (n + kBlock - 1) / kBlock;
+    int64_t cap = (int64_t)P->n_cu * per_cu;
+    return (int)std::max<int64_t>(1, std::min<int64_t>({want, cap, (int64_t)kMaxBlocks}));
+}
+
+template <class R, bool COMP>
+int launch_trace(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
+{
+    Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
+    Geo g = make_geo(P);
+    auto kern = P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4> : k_trace<R, COMP, 2>;
+    int blocks = grid_blocks(P, kern, A.n_pairs);
+    P->stat_blocks_trace = blocks;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, M, g, A);
+    HIP_TRY(hipGetLastError());
+    return RTX_OK;
+}
+
+template <class R, bool COMP>
+int launch_adjoint(rtx_plan_s *P, const AdjArgs &A, R *grad, hipStream_t s)
+{
+    Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
+    Geo g = make_geo(P);
+    auto kern = P->opts.integ == RTX_RK4 ? k_adjoint<R, COMP, 4> : k_adjoint<R, COMP, 2>;
+    int blocks = grid_blocks(P, kern, A.n_pairs);
+    P->stat_blocks_adj = blocks;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, M, g, A, grad);
+    HIP_TRY(hipGetLastError());
+    return RTX_OK;
+}
+
+int check_pairs(const rtx_plan_s *P, const int32_t *pairs, int64_t n)
+{
+    if (n < 0) return fail(RTX_E_ARG, "n_pairs < 0");
+    if (n > P->max_pairs) return fail(RTX_E_ARG, "n_pairs %lld exceeds the plan's max_pairs %lld", (long long)n,
+                                      (long long)P->max_pairs);
+    if (!pairs && n != 0 && n != (int64_t)P->ring.n_elem * (P->ring.n_elem - 1))
+        return fail(RTX_E_ARG, "pairs == NULL requires n_pairs = n_elem (n_elem - 1)");
+    return RTX_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI ==
+extern "C" {
+
+const char *rtx_last_error(void) { return g_last_error.c_str(); }
+
+int rtx_plan_create(rtx_plan *out, const rtx_grid *grid, const rtx_ring *ring, const rtx_opts *opts,
+                    int64_t max_pairs)
+{
+    g_last_error.clear();
+    if (!out) return fail(RTX_E_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_opts(grid, ring, opts);
+    if (rc) return rc;
+    if (max_pairs < 1) return fail(RTX_E_ARG, "max_pairs must be >= 1");
+    rtx_plan_s *P = new rtx_plan_s();
+    P->grid = *grid;
+    P->ring = *ring;
+    P->opts = *opts;
+    P->max_pairs = max_pairs;
+    size_t esz = opts->prec == RTX_F32C ? sizeof(float) : sizeof(double);
+    size_t tab_bytes = (size_t)(grid->nx - 1) * (grid->ny - 1) * kCoef * esz;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete P;
+        return fail(RTX_E_HIP, "no HIP device");
+    }
+    P->n_cu = prop.multiProcessorCount;
+    if (hipMalloc(&P->tab, tab_bytes) != hipSuccess ||
+        hipMalloc((void **)&P->stats, sizeof(unsigned long long) * 2 * kMaxBlocks * 2) != hipSuccess ||
+        hipMalloc((void **)&P->rho, sizeof(double) * max_pairs) != hipSuccess) {
+        rtx_plan_destroy(P);
+        return fail(RTX_E_NOMEM, "device allocation of the plan workspace failed");
+    }
+    *out = P;
+    return RTX_OK;
+}
+
+int rtx_plan_destroy(rtx_plan P)
+{
+    if (!P) return RTX_OK;
+    (void)hipDeviceSynchronize();
+    if (P->tab) (void)hipFree(P->tab);
+    if (P->stats) (void)hipFree(P->stats);
+    if (P->rho) (void)hipFree(P->rho);
+    if (P->omega) (void)hipFree(P->omega);
+    delete P;
+    return RTX_OK;
+}
+
+int rtx_plan_set_opts(rtx_plan P, const rtx_opts *opts)
+{
+    g_last_error.clear();
+    if (!P || !opts) return fail(RTX_E_ARG, "null plan/opts");
+    if (opts->prec != P->opts.prec) return fail(RTX_E_ARG, "precision of a plan cannot change");
+    int rc = check_opts(&P->grid, &P->ring, opts);
+    if (rc) return rc;
+    P->opts = *opts;
+    return RTX_OK;
+}
+
+int rtx_set_medium(rtx_plan P, const double *c, void *stream)
+{
+    g_last_error.clear();
+    if (!P || !c) return fail(RTX_E_ARG, "null plan or c");
+    return pack(P, c, (hipStream_t)stream);
+}
+
+int rtx_trace_rays(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_pairs, double *theta,
+                   double *tof, double *len, double *miss_px, int32_t *n_marches, int8_t *status,
+                   int64_t *w_rowptr, int32_t *w_col, void *w_val, int64_t nnz_cap, void *stream)
+{
+    g_last_error.clear();
+    if (!P) return fail(RTX_E_ARG, "null plan");
+    int rc = check_pairs(P, pairs, n_pairs);
+    if (rc) return rc;
+    if (!theta || !status) return fail(RTX_E_ARG, "theta and status are required");
+    if (w_rowptr || w_col || w_val) return fail(RTX_E_UNSUPPORTED, "path-weight emission is not available");
+    (void)nnz_cap;
+    hipStream_t s = (hipStream_t)stream;
+    rc = pack(P, c, s);
+    if (rc) return rc;
+    if (n_pairs == 0) return RTX_OK;
+    TraceArgs A;
+    A.pairs = pairs;
+    A.n_pairs = n_pairs;
+    A.theta = theta;
+    A.tof = tof;
+    A.len = len;
+    A.miss = miss_px;
+    A.n_marches = n_marches;
+    A.status = status;
+    A.max_marches = P->opts.max_marches;
+    A.max_steps = max_steps_of(P);
+    A.tol = P->opts.tol_px;
+    A.flags = P->opts.flags;
+    A.stats = P->stats;
+    if (P->opts.prec == RTX_F32C) return launch_trace<float, true>(P, A, s);
+    return launch_trace<double, false>(P, A, s);
+}
+
+int rtx_tof_forward(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_pairs, double *theta,
+                    double *tof, int8_t *status, void *stream)
+{
+    return rtx_trace_rays(P, c, pairs, n_pairs, theta, tof, nullptr, nullptr, nullptr, status, nullptr, nullptr,
+                          nullptr, 0, stream);
+}
+
+int rtx_tof_adjoint(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_pairs, const double *theta,
+                    const int8_t *status, const double *tof, const void *resid, int32_t resid_kind,
+                    const double *freqs_hz, int32_t n_freq, int32_t weight, void *grad, void *stream)
+{
+    g_last_error.clear();
+    if (!P) return fail(RTX_E_ARG, "null plan");
+    int rc = check_pairs(P, pairs, n_pairs);
+    if (rc) return rc;
+    if (!theta || !status || !resid || !grad) return fail(RTX_E_ARG, "theta, status, resid and grad are required");
+    if (weight != RTX_W_LENGTH && weight != RTX_W_DTDC) return fail(RTX_E_ARG, "unknown weight %d", weight);
+    if (resid_kind != RTX_RESID_REAL && resid_kind != RTX_RESID_RAYBORN_C64)
+        return fail(RTX_E_ARG, "unknown resid_kind %d", resid_kind);
+    hipStream_t s = (hipStream_t)stream;
+    const double *rho = (const double *)resid;
+    if (resid_kind == RTX_RESID_RAYBORN_C64) {
+        if (!tof || !freqs_hz || n_freq < 1) return fail(RTX_E_ARG, "ray-Born residuals need tof and freqs_hz");
+        if (n_freq > P->n_freq_cap) {
+            if (P->omega) {
+                HIP_TRY(hipStreamSynchronize(s));
+                (void)hipFree(P->omega);
+                P->omega = nullptr;
+            }
+            if (hipMalloc((void **)&P->omega, sizeof(double) * n_freq) != hipSuccess)
+                return fail(RTX_E_NOMEM, "omega buffer");
+            P->n_freq_cap = n_freq;
+        }
+        std::vector<double> om(n_freq);
+        for (int k = 0; k < n_freq; k++) om[k] = 2.0 * kPi * freqs_hz[k];
+        HIP_TRY(hipMemcpyAsync(P->omega, om.data(), sizeof(double) * n_freq, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // `om` is pageable host memory
+        if (n_pairs > 0) {
+            int64_t blocks = (n_pairs * 64 + kBlock - 1) / kBlock;
+            hipLaunchKernelGGL(k_rayborn_rho, dim3((unsigned)blocks), dim3(kBlock), 0, s, n_pairs, n_freq, tof,
+                               P->omega, (const float2 *)resid, P->rho);
+            HIP_TRY(hipGetLastError());
+        }
+        rho = P->rho;
+    }
+    rc = pack(P, c, s);
+    if (rc) return rc;
+    if (n_pairs == 0) return RTX_OK;
+    AdjArgs A;
+    A.pairs = pairs;
+    A.n_pairs = n_pairs;
+    A.theta = theta;
+    A.status = status;
+    A.rho = rho;
+    A.weight = weight;
+    A.max_steps = max_steps_of(P);
+    A.stats = P->stats + 2 * kMaxBlocks;
+    if (P->opts.prec == RTX_F32C) return launch_adjoint<float, true>(P, A, (float *)grad, s);
+    return launch_adjoint<double, false>(P, A, (double *)grad, s);
+}
+
+int rtx_plan_stats(rtx_plan P, int64_t *trace_steps, int64_t *trace_rays, int64_t *adjoint_steps)
+{
+    g_last_error.clear();
+    if (!P) return fail(RTX_E_ARG, "null plan");
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<unsigned long long> h(4 * kMaxBlocks);
+    HIP_TRY(hipMemcpy(h.data(), P->stats, sizeof(unsigned long long) * 4 * kMaxBlocks, hipMemcpyDeviceToHost));
+    unsigned long long ts = 0, tr = 0, as = 0;
+    for (int b = 0; b < P->stat_blocks_trace; b++) {
+        ts += h[2 * b];
+        tr += h[2 * b + 1];
+    }
+    for (int b = 0; b < P->stat_blocks_adj; b++) as += h[2 * kMaxBlocks + 2 * b];
+    if (trace_steps) *trace_steps = (int64_t)ts;
+    if (trace_rays) *trace_rays = (int64_t)tr;
+    if (adjoint_steps) *adjoint_steps = (int64_t)as;
+    return RTX_OK;
+}
+
+}  // extern "C"

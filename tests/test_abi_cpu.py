@@ -1,0 +1,64 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/rtx.h declares, and the Python structs match the C
+layout."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rtx.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2511_18511_amd import _binding, build
+
+    if not os.path.exists(_binding.LIB_PATH):
+        build.build()
+    return _binding.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(rtx_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("rtx_trace_rays", "rtx_tof_forward", "rtx_tof_adjoint", "rtx_plan_create", "rtx_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2511_18511_amd import _binding
+
+    names = declared_functions()
+    assert sorted(_binding.EXPORTS) == names
+    out = subprocess.run(["nm", "-D", "--defined-only", _binding.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (rtx_\w+)", out))
+    assert set(names) <= exported
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_struct_layouts_match_c():
+    from paper_2511_18511_amd import _binding as B
+
+    assert C.sizeof(B.rtx_grid) == 16 and B.rtx_grid.h.offset == 8
+    assert C.sizeof(B.rtx_ring) == 24 and B.rtx_ring.radius.offset == 8
+    assert C.sizeof(B.rtx_opts) == 40 and B.rtx_opts.flags.offset == 32
+
+
+def test_no_cpu_fallback_in_product_path():
+    """The package never imports the oracle and has no host compute path."""
+    pkg = os.path.join(ROOT, "paper_2511_18511_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "oracle_rt" not in text, f

@@ -1,0 +1,240 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Fixed-angle traces are unique results: T, L, miss and status are compared pair
+by pair.  A linked angle is one of many valid results (any angle whose miss is
+within the tolerance), so linked runs are checked by (a) re-tracing the GPU's
+angle in the oracle (T, L, miss <= tol), (b) the same root as the oracle's own
+linking, and (c) pair-by-pair T agreement where both took the same number of
+rays (FP64)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rtx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2511_18511_amd as rtx
+
+    return rtx
+
+
+DEV = "cuda:0"
+TOL_T = {"f64": 1e-12, "f32c": 1e-5}
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _gauss(n=96, h=0.5e-3, seed=21):
+    return synth.gaussian_inclusions(n, n, h, seed=seed, r_max=0.7 * 0.45 * n * h)
+
+
+def _fixed_case(rtx, prec, c, h, ring, pairs, theta, integ="rk4", ds=0.25):
+    n_elem, radius, phi0 = ring
+    ny, nx = c.shape
+    plan = rtx.Plan(nx, ny, h, n_elem, radius, phi0, prec=prec, integ=integ, ds_px=ds, max_pairs=len(pairs))
+    out = plan.trace(_dev(c), pairs=_dev(pairs.astype(np.int32)), theta=_dev(theta), fixed=True)
+    ref = oracle.trace(oracle.grid_medium(c, h), ring, pairs, theta=theta, fixed=True, integ=integ, ds_px=ds)
+    plan.close()
+    return {k: _np(v) for k, v in out.items()}, ref
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+@pytest.mark.parametrize("integ", ["rk4", "heun"])
+def test_fixed_angle_matches_oracle(rtx, prec, integ):
+    """Several tiles of lanes plus a ragged tail (1000 pairs), random angles."""
+    n, h = 96, 0.5e-3
+    c = _gauss(n, h)
+    ring = (40, 0.45 * n * h * 0.9, 0.1)
+    rng = np.random.default_rng(0)
+    allp = synth.all_pairs(40)
+    pairs = allp[rng.choice(len(allp), 1000, replace=False)]
+    theta = rng.uniform(-1.4, 1.4, len(pairs))
+    out, ref = _fixed_case(rtx, prec, c, h, ring, pairs, theta, integ)
+    assert np.array_equal(out["status"], ref["status"])
+    hit = ref["status"] == oracle.LINKED
+    assert hit.sum() > 900
+    rel = np.abs(out["tof"][hit] / ref["tof"][hit] - 1)
+    assert rel.max() < TOL_T[prec], rel.max()
+    assert np.abs(out["len"][hit] / ref["len"][hit] - 1).max() < TOL_T[prec]
+    assert np.abs(out["miss_px"][hit] - ref["miss_px"][hit]).max() < (1e-9 if prec == "f64" else 2e-4)
+    assert np.all(out["n_marches"] == 1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_linked_fisheye_c1(rtx, prec):
+    """The 128x128 fish-eye workload, all 992 pairs (strong focusing: reversed
+    misfit orientation, trapped near-grazing rays)."""
+    cfg, c = synth.make_config("c1_fisheye_128")
+    ring = (cfg["n_elem"], cfg["radius"], cfg["phi0"])
+    pairs = synth.all_pairs(cfg["n_elem"])
+    plan = rtx.Plan(cfg["nx"], cfg["ny"], cfg["h"], *ring, prec=prec)
+    out = {k: _np(v) for k, v in plan.trace(_dev(c)).items()}
+    plan.close()
+    ref = oracle.trace(oracle.grid_medium(c, cfg["h"]), ring, pairs)
+    _check_linked(out, ref, c, cfg["h"], ring, pairs, prec, cfg["tol_px"])
+
+
+def _check_linked(out, ref, c, h, ring, pairs, prec, tol, idx=None):
+    if idx is None:
+        idx = np.arange(len(pairs))
+    st = out["status"][idx]
+    assert np.array_equal(st, ref["status"]), (np.bincount(st, minlength=4), np.bincount(ref["status"], minlength=4))
+    ok = st == oracle.LINKED
+    # (a) the oracle re-traces the GPU's angle: same T/L, and it really links
+    chk = oracle.trace(oracle.grid_medium(c, h), ring, pairs[idx][ok], theta=out["theta"][idx][ok], fixed=True)
+    assert np.abs(out["tof"][idx][ok] / chk["tof"] - 1).max() < TOL_T[prec]
+    assert np.abs(out["len"][idx][ok] / chk["len"] - 1).max() < TOL_T[prec]
+    assert chk["miss_px"].max() <= tol * (1 + 1e-6) + (0 if prec == "f64" else 2e-4)
+    # (b) the same root as the oracle's own linking: angles within the tolerance
+    # band (|dg/dtheta| >= 0.05 on these workloads) and T within the band it spans
+    R_px = ring[1] / h
+    dth = np.abs(out["theta"][idx][ok] - ref["theta"][ok])
+    assert dth.max() < 4 * tol / R_px / 0.05
+    cmin = c.min()
+    assert np.abs(out["tof"][idx][ok] - ref["tof"][ok]).max() < 4 * tol * h / cmin + 1e-5 * ref["tof"][ok].max()
+    # (c) FP64 with the same number of rays: same iterates, T to 1e-10
+    if prec == "f64":
+        same = out["n_marches"][idx][ok] == ref["n_marches"][ok]
+        assert same.mean() > 0.95
+        assert np.abs(out["tof"][idx][ok][same] / ref["tof"][ok][same] - 1).max() < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_linked_gaussian_sampled_full_size(rtx, prec):
+    """256x256 Gaussian-inclusion workload (65,280 pairs) traced in full on the
+    GPU in the benchmark's launch configuration; 600 sampled pairs checked
+    against the oracle."""
+    cfg, c = synth.make_config("c2_gauss_256")
+    ring = (cfg["n_elem"], cfg["radius"], cfg["phi0"])
+    pairs = synth.all_pairs(cfg["n_elem"])
+    plan = rtx.Plan(cfg["nx"], cfg["ny"], cfg["h"], *ring, prec=prec)
+    out = {k: _np(v) for k, v in plan.trace(_dev(c)).items()}
+    plan.close()
+    assert np.all(out["status"] == oracle.LINKED)
+    idx = np.sort(np.random.default_rng(3).choice(len(pairs), 600, replace=False))
+    ref = oracle.trace(oracle.grid_medium(c, cfg["h"]), ring, pairs[idx])
+    _check_linked(out, ref, c, cfg["h"], ring, pairs, prec, cfg["tol_px"], idx)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_warm_start_and_explicit_pairs(rtx, prec):
+    n, h = 96, 0.5e-3
+    c = _gauss(n, h, seed=4)
+    ring = (24, 0.45 * n * h * 0.9, 0.0)
+    pairs = synth.all_pairs(24)[::3].copy()
+    ref = oracle.trace(oracle.grid_medium(c, h), ring, pairs)
+    plan = rtx.Plan(n, n, h, *ring, prec=prec, max_pairs=len(pairs))
+    th0 = ref["theta"] + 1e-3
+    out = {k: _np(v) for k, v in plan.trace(_dev(c), pairs=_dev(pairs), theta=_dev(th0), warm=True).items()}
+    plan.close()
+    refw = oracle.trace(oracle.grid_medium(c, h), ring, pairs, theta=th0, warm=True)
+    assert np.all(out["status"] == oracle.LINKED)
+    assert np.all(out["n_marches"] <= 3)
+    _check_linked(out, refw, c, h, ring, pairs, prec, 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+@pytest.mark.parametrize("weight", ["length", "dtdc"])
+def test_adjoint_matches_oracle(rtx, prec, weight):
+    n, h = 96, 0.5e-3
+    c = _gauss(n, h, seed=8)
+    ring = (32, 0.45 * n * h * 0.9, 0.0)
+    pairs = synth.all_pairs(32)
+    ref = oracle.trace(oracle.grid_medium(c, h), ring, pairs)
+    rho = synth.real_residual(len(pairs), 2002)
+    plan = rtx.Plan(n, n, h, *ring, prec=prec)
+    g = plan.adjoint(_dev(ref["theta"]), _dev(ref["status"]), _dev(rho), weight=weight, c=_dev(c))
+    plan.close()
+    gref = oracle.adjoint(c, h, ring, pairs, ref["theta"], rho, weight=weight, status=ref["status"])
+    err = np.linalg.norm(_np(g).astype(np.float64) - gref) / np.linalg.norm(gref)
+    assert err < (1e-11 if prec == "f64" else 1e-5), err
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_rayborn_adjoint_matches_oracle(rtx, prec):
+    n, h = 96, 0.5e-3
+    c = _gauss(n, h, seed=12)
+    ring = (24, 0.45 * n * h * 0.9, 0.0)
+    pairs = synth.all_pairs(24)
+    ref = oracle.trace(oracle.grid_medium(c, h), ring, pairs)
+    freqs = np.linspace(0.5e6, 1.5e6, 64)
+    r = synth.complex_residual(len(pairs), 64, 2004)
+    plan = rtx.Plan(n, n, h, *ring, prec=prec)
+    g = plan.adjoint(_dev(ref["theta"]), _dev(ref["status"]), _dev(r), weight="length", c=_dev(c),
+                     tof=_dev(ref["tof"]), freqs_hz=list(freqs))
+    plan.close()
+    rho = oracle.rayborn_rho(ref["tof"], freqs, r)
+    gref = oracle.adjoint(c, h, ring, pairs, ref["theta"], rho, weight="length", status=ref["status"])
+    err = np.linalg.norm(_np(g).astype(np.float64) - gref) / np.linalg.norm(gref)
+    assert err < (1e-11 if prec == "f64" else 1e-5), err
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_status_paths_match_oracle(rtx, prec):
+    n, h = 64, 1e-3
+    c = synth.gaussian_inclusions(n, n, h, seed=11, r_max=0.015)
+    ring = (16, 0.025, 0.0)
+    pairs = np.array([[0, 5], [3, 3], [2, 16], [-1, 4], [7, 2]], np.int32)
+    plan = rtx.Plan(n, n, h, *ring, prec=prec, max_pairs=16)
+    for over, kw in (({}, {}), ({"max_marches": 1}, {"max_marches": 1}), ({"tol_px": 0.0, "max_marches": 4},
+                     {"tol_px": 0.0, "max_marches": 4}), ({"max_steps": 3}, {"max_steps": 3})):
+        out = {k: _np(v) for k, v in plan.trace(_dev(c), pairs=_dev(pairs), **over).items()}
+        ref = oracle.trace(oracle.grid_medium(c, h), ring, pairs, **kw)
+        assert np.array_equal(out["status"], ref["status"]), (over, out["status"], ref["status"])
+        assert np.array_equal(out["n_marches"][ref["status"] != oracle.BAD_INPUT],
+                              ref["n_marches"][ref["status"] != oracle.BAD_INPUT])
+    for bad in (np.nan, -1.0):
+        cb = c.copy()
+        cb[30:34, 28:36] = bad
+        out = {k: _np(v) for k, v in plan.trace(_dev(cb), pairs=_dev(np.array([[0, 8], [4, 12]], np.int32))).items()}
+        ref = oracle.trace(oracle.grid_medium(cb, h), ring, np.array([[0, 8], [4, 12]], np.int32))
+        assert np.array_equal(out["status"], ref["status"])
+    # empty batch
+    e = plan.trace(_dev(c), pairs=_dev(np.zeros((0, 2), np.int32)))
+    assert e["tof"].numel() == 0
+    plan.close()
+
+
+def test_argument_errors(rtx):
+    with pytest.raises(rtx.RtxError):
+        rtx.Plan(64, 64, 1e-3, 16, 0.040)  # ring does not fit the grid
+    with pytest.raises(rtx.RtxError):
+        rtx.Plan(64, 64, 1e-3, 16, 0.020, ds_px=3.0)
+    plan = rtx.Plan(64, 64, 1e-3, 16, 0.020, max_pairs=10)
+    with pytest.raises(rtx.RtxError):
+        plan.trace(_dev(np.full((64, 64), 1500.0)))  # 240 pairs > max_pairs
+    with pytest.raises(rtx.RtxError):
+        plan.trace(None, pairs=_dev(np.zeros((2, 2), np.int32)))  # no medium set
+    plan.close()
+
+
+def test_fisheye_f64_linked_matches_closed_form(rtx):
+    """Closed form through the GPU path: gridded fish-eye T within the bilinear
+    bias of the analytic travel time."""
+    from tests import closed_form as cf
+
+    cfg, c = synth.make_config("c1_fisheye_128")
+    ring = (cfg["n_elem"], cfg["radius"], 0.0)
+    plan = rtx.Plan(cfg["nx"], cfg["ny"], cfg["h"], *ring, prec="f64")
+    out = {k: _np(v) for k, v in plan.trace(_dev(c)).items()}
+    plan.close()
+    pts, _ = cf.ring_points(*ring)
+    T = np.array([cf.fisheye_tof(pts[e], pts[r], 1500.0, 0.040) for e, r in synth.all_pairs(32)])
+    assert np.max(np.abs(out["tof"] / T - 1)) < 5e-4
+    assert math.isfinite(out["tof"].sum())
