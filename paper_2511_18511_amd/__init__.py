@@ -84,9 +84,11 @@ class Plan:
         _dev_check(pairs, torch.int32, None, "pairs")
         return pairs, pairs.shape[0]
 
-    def trace(self, c=None, pairs=None, theta=None, warm=False, fixed=False, out=None, **over):
+    def trace(self, c=None, pairs=None, theta=None, warm=False, fixed=False, out=None, weights=False, **over):
         """Linked (or fixed-angle) tracing.  Returns a dict of device tensors:
-        theta, tof (s), len (m), miss_px, n_marches, status."""
+        theta, tof (s), len (m), miss_px, n_marches, status, and with
+        weights=True the system matrix of the traced rays (w_rowptr, w_col,
+        w_val; see weights())."""
         if c is not None:
             _dev_check(c, torch.float64, (self.ny, self.nx), "c")
         pairs, n = self._pairs(pairs)
@@ -107,7 +109,30 @@ class Plan:
         B.rtx_trace_rays(self._handle, _ptr(c), _ptr(pairs), n, _ptr(out["theta"]), _ptr(out.get("tof")),
                          _ptr(out.get("len")), _ptr(out.get("miss_px")), _ptr(out.get("n_marches")),
                          _ptr(out["status"]), None, None, None, 0, _stream())
+        if weights:
+            out["w_rowptr"], out["w_col"], out["w_val"] = self.weights(out["theta"], pairs=pairs, **over)
         return out
+
+    def weights(self, theta, pairs=None, **over):
+        """System-matrix rows W_ij = h sum_m w_m phi_j(p_m) of the rays traced at
+        the given angles, as CSR device tensors (rowptr int64 [n+1], col int32
+        ascending per row, val float/double per precision, metres).  Rows of
+        rays that do not reach the ring are empty."""
+        pairs, n = self._pairs(pairs)
+        _dev_check(theta, torch.float64, (n,), "theta")
+        dev = theta.device
+        th = theta.clone()
+        st = torch.empty(n, dtype=torch.int8, device=dev)
+        rowptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+        self._apply(B.RTX_FIXED_ANGLE, **over)
+        B.rtx_trace_rays(self._handle, None, _ptr(pairs), n, _ptr(th), None, None, None, None, _ptr(st),
+                         _ptr(rowptr), None, None, 0, _stream())
+        nnz = int(rowptr[-1].item())
+        col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        val = torch.empty(max(nnz, 1), dtype=self.real, device=dev)
+        B.rtx_trace_rays(self._handle, None, _ptr(pairs), n, _ptr(th), None, None, None, None, _ptr(st),
+                         _ptr(rowptr), _ptr(col), _ptr(val), nnz, _stream())
+        return rowptr, col[:nnz], val[:nnz]
 
     def adjoint(self, theta, status, resid, weight="length", c=None, pairs=None, tof=None, freqs_hz=None,
                 grad=None, **over):

@@ -126,6 +126,14 @@ __device__ __forceinline__ void two_sum(R a, R b, R &s, R &e)
     e = (a - (s - bb)) + (b - bb);
 }
 
+// Error-free sum when |a| >= |b| or a == 0 (Dekker): a + b = s + e exactly.
+template <class R>
+__device__ __forceinline__ void fast_two_sum(R a, R b, R &s, R &e)
+{
+    s = a + b;
+    e = b - (s - a);
+}
+
 // ----------------------------------------------------------- medium lookup --
 template <class R>
 struct Medium {
@@ -133,18 +141,20 @@ struct Medium {
     int nx, ny;
 };
 
-__device__ __forceinline__ void load_cell(const float *tab, int cell, float (&v)[12])
+// Cells are addressed with 32-bit byte offsets from the table base (tables are
+// far below 4 GiB), so the loads take the scalar-base + 32-bit offset form.
+__device__ __forceinline__ void load_cell(const float *tab, uint32_t cell, float (&v)[12])
 {
-    const float4 *p = reinterpret_cast<const float4 *>(tab) + 3 * (size_t)cell;
+    const float4 *p = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tab) + __umul24(cell, 48u));
     float4 a = p[0], b = p[1], c = p[2];
     v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w;
     v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
     v[8] = c.x, v[9] = c.y, v[10] = c.z, v[11] = c.w;
 }
 
-__device__ __forceinline__ void load_cell(const double *tab, int cell, double (&v)[12])
+__device__ __forceinline__ void load_cell(const double *tab, uint32_t cell, double (&v)[12])
 {
-    const double2 *p = reinterpret_cast<const double2 *>(tab) + 6 * (size_t)cell;
+    const double2 *p = reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(tab) + __umul24(cell, 96u));
     for (int k = 0; k < 6; k++) {
         double2 a = p[k];
         v[2 * k] = a.x;
@@ -166,16 +176,19 @@ template <class R>
 __device__ __forceinline__ Sample<R> lookup(const Medium<R> &M, R uh, R du, R vh, R dv)
 {
     Sample<R> o;
-    R fu = floor_(uh + du), fv = floor_(vh + dv);
-    fu = fmin_(fmax_(fu, (R)0), (R)(M.nx - 2));
-    fv = fmin_(fmax_(fv, (R)0), (R)(M.ny - 2));
+    // cell index = floor of the coordinate, clamped to the grid; the float->int
+    // conversion truncates (equal to floor for the non-negative coordinates that
+    // survive the clamp), maps NaN to 0 and saturates, so any position gives an
+    // in-bounds cell
+    o.ix = min(max((int)(uh + du), 0), M.nx - 2);
+    o.iy = min(max((int)(vh + dv), 0), M.ny - 2);
+    R fu = (R)o.ix, fv = (R)o.iy;
     R t = (uh - fu) + du, s = (vh - fv) + dv;
     o.t = fmin_(fmax_(t, (R)0), (R)1);
     o.s = fmin_(fmax_(s, (R)0), (R)1);
-    o.ix = (int)fu;
-    o.iy = (int)fv;
     R v[12];
-    load_cell(M.tab, o.iy * (M.nx - 1) + o.ix, v);
+    // 24-bit multiplies: plans keep (nx-1)(ny-1) below 2^24 cells
+    load_cell(M.tab, __umul24((uint32_t)o.iy, (uint32_t)(M.nx - 1)) + (uint32_t)o.ix, v);
     o.c = fma(o.s, fma(o.t, v[3], v[2]), fma(o.t, v[1], v[0]));
     o.gx = fma(o.s, fma(o.t, v[7], v[6]), fma(o.t, v[5], v[4]));
     o.gy = fma(o.s, fma(o.t, v[11], v[10]), fma(o.t, v[9], v[8]));
@@ -231,30 +244,42 @@ struct StepOut {
     R ic1;
 };
 
+// Keeps a value computed here: stops the compiler from sinking its producer (a
+// table lookup) below the caller's crossing test.
+template <class R>
+__device__ __forceinline__ void materialize(R &x)
+{
+    asm volatile("" : "+v"(x));
+}
+
 template <class R, bool COMP, int INTEG>
 __device__ __forceinline__ StepOut<R> ray_step(const Medium<R> &M, const Ray<R> &y, Ray<R> &nxt, R ds)
 {
     StepOut<R> o;
     const R d1x = y.dxh + y.dxl, d1y = y.dyh + y.dyl;
-    o.s1 = lookup(M, y.uh, y.ul, y.vh, y.vl);
-    o.ic1 = rcp(o.s1.c);
-    R k1x, k1y;
-    curvature(o.s1, o.ic1, d1x, d1y, k1x, k1y);
     R incx, incy, idx, idy;
     if (INTEG == 4) {
+        // RK4 stage points: x, x + ds/2 d1, x + ds/2 d2, x + ds d3.  The first two
+        // depend only on the state and the last two only on k1 and k2, so the
+        // lookups go out in two dependent pairs: one step costs two memory
+        // round trips instead of four.
         const R h2 = ds * (R)0.5;
-        R d2x = fma(h2, k1x, d1x), d2y = fma(h2, k1y, d1y);
+        o.s1 = lookup(M, y.uh, y.ul, y.vh, y.vl);
         Sample<R> s2 = lookup(M, y.uh, fma(h2, d1x, y.ul), y.vh, fma(h2, d1y, y.vl));
-        R k2x, k2y;
+        o.ic1 = rcp(o.s1.c);
+        R k1x, k1y, k2x, k2y;
+        curvature(o.s1, o.ic1, d1x, d1y, k1x, k1y);
+        R d2x = fma(h2, k1x, d1x), d2y = fma(h2, k1y, d1y);
         curvature(s2, rcp(s2.c), d2x, d2y, k2x, k2y);
         R d3x = fma(h2, k2x, d1x), d3y = fma(h2, k2y, d1y);
         Sample<R> s3 = lookup(M, y.uh, fma(h2, d2x, y.ul), y.vh, fma(h2, d2y, y.vl));
-        R k3x, k3y;
+        Sample<R> s4 = lookup(M, y.uh, fma(ds, d3x, y.ul), y.vh, fma(ds, d3y, y.vl));
+        R k3x, k3y, k4x, k4y;
         curvature(s3, rcp(s3.c), d3x, d3y, k3x, k3y);
         R d4x = fma(ds, k3x, d1x), d4y = fma(ds, k3y, d1y);
-        Sample<R> s4 = lookup(M, y.uh, fma(ds, d3x, y.ul), y.vh, fma(ds, d3y, y.vl));
-        R k4x, k4y;
         curvature(s4, rcp(s4.c), d4x, d4y, k4x, k4y);
+        materialize(k4x);
+        materialize(k4y);
         // x+ = x + ds/6 (d1 + 2 d2 + 2 d3 + d4) = x + ds d1 + ds^2/6 (k1 + k2 + k3)
         const R c6 = ds * ds * (R)(1.0 / 6.0), s6 = ds * (R)(1.0 / 6.0);
         incx = fma(c6, k1x + k2x + k3x, ds * d1x);
@@ -262,10 +287,16 @@ __device__ __forceinline__ StepOut<R> ray_step(const Medium<R> &M, const Ray<R> 
         idx = s6 * (k1x + (R)2 * (k2x + k3x) + k4x);
         idy = s6 * (k1y + (R)2 * (k2y + k3y) + k4y);
     } else {
-        R d2x = fma(ds, k1x, d1x), d2y = fma(ds, k1y, d1y);
+        // Heun stage points x and x + ds d1: both known up front, one round trip
+        o.s1 = lookup(M, y.uh, y.ul, y.vh, y.vl);
         Sample<R> s2 = lookup(M, y.uh, fma(ds, d1x, y.ul), y.vh, fma(ds, d1y, y.vl));
-        R k2x, k2y;
+        o.ic1 = rcp(o.s1.c);
+        R k1x, k1y, k2x, k2y;
+        curvature(o.s1, o.ic1, d1x, d1y, k1x, k1y);
+        R d2x = fma(ds, k1x, d1x), d2y = fma(ds, k1y, d1y);
         curvature(s2, rcp(s2.c), d2x, d2y, k2x, k2y);
+        materialize(k2x);
+        materialize(k2y);
         // x+ = x + ds/2 (d1 + d2) = x + ds d1 + ds^2/2 k1
         incx = fma(ds * ds * (R)0.5, k1x, ds * d1x);
         incy = fma(ds * ds * (R)0.5, k1y, ds * d1y);
@@ -274,10 +305,13 @@ __device__ __forceinline__ StepOut<R> ray_step(const Medium<R> &M, const Ray<R> 
     }
     if (COMP) {
         R s, e;
-        two_sum(y.uh, incx, s, e);
+        // inside the ring a grid coordinate is at least max(1, ds) (the plan's
+        // margin) >= |inc|, which is what the fast form needs; on the step that
+        // leaves the ring a violated precondition only costs a rounding-level error
+        fast_two_sum(y.uh, incx, s, e);
         nxt.uh = s;
         nxt.ul = y.ul + e;
-        two_sum(y.vh, incy, s, e);
+        fast_two_sum(y.vh, incy, s, e);
         nxt.vh = s;
         nxt.vl = y.vl + e;
         two_sum(y.dxh, idx, s, e);
@@ -313,7 +347,7 @@ __device__ __forceinline__ void add_T(Ray<R> &y, R term)
 {
     if (COMP) {
         R s, e;
-        two_sum(y.Th, term, s, e);
+        fast_two_sum(y.Th, term, s, e);  // Th is 0 or a sum of positive terms >= term
         y.Th = s;
         y.Tl += e;
     } else {
@@ -635,15 +669,41 @@ struct AdjArgs {
     unsigned long long *stats;
 };
 
+// Pending hat weights of one cell visit.  Consecutive samples of a ray that
+// fall in the same cell add into registers; the four node atomics go out when
+// the ray leaves the cell (about one flush per 3-4 samples at ds = 0.25 px).
 template <class R>
-__device__ __forceinline__ void scatter4(R *grad, int nx, const Sample<R> &s, R a)
+struct CellAcc {
+    int64_t n0;  // node index of the cell's lower-left corner, -1 = empty
+    R a00, a10, a01, a11;
+};
+
+template <class R>
+__device__ __forceinline__ void acc_flush(R *grad, int nx, CellAcc<R> &A)
 {
+    if (A.n0 >= 0) {
+        unsafeAtomicAdd(grad + A.n0, A.a00);
+        unsafeAtomicAdd(grad + A.n0 + 1, A.a10);
+        unsafeAtomicAdd(grad + A.n0 + nx, A.a01);
+        unsafeAtomicAdd(grad + A.n0 + nx + 1, A.a11);
+    }
+    A.n0 = -1;
+    A.a00 = A.a10 = A.a01 = A.a11 = (R)0;
+}
+
+template <class R>
+__device__ __forceinline__ void acc_add(R *grad, int nx, CellAcc<R> &A, const Sample<R> &s, R a)
+{
+    int64_t n0 = (int64_t)s.iy * nx + s.ix;
+    if (n0 != A.n0) {
+        acc_flush(grad, nx, A);
+        A.n0 = n0;
+    }
     R omt = (R)1 - s.t, oms = (R)1 - s.s;
-    size_t n0 = (size_t)s.iy * nx + s.ix;
-    unsafeAtomicAdd(grad + n0, a * omt * oms);
-    unsafeAtomicAdd(grad + n0 + 1, a * s.t * oms);
-    unsafeAtomicAdd(grad + n0 + nx, a * omt * s.s);
-    unsafeAtomicAdd(grad + n0 + nx + 1, a * s.t * s.s);
+    A.a00 = fma(a * omt, oms, A.a00);
+    A.a10 = fma(a * s.t, oms, A.a10);
+    A.a01 = fma(a * omt, s.s, A.a01);
+    A.a11 = fma(a * s.t, s.s, A.a11);
 }
 
 template <class R, bool COMP, int INTEG>
@@ -656,6 +716,9 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
     const R cx = (R)g.cx, cy = (R)g.cy;
     unsigned long long n_steps = 0, n_rays = 0;
     Ray<R> ray;
+    CellAcc<R> acc;
+    acc.n0 = -1;
+    acc.a00 = acc.a10 = acc.a01 = acc.a11 = (R)0;
     R scale = 0;  // rho h
     bool active = false;
     TraceArgs pa;
@@ -690,7 +753,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
         const bool exhausted = !bad && !crossed && (ray.m + 1 >= A.max_steps);
         if (!(bad || crossed || exhausted)) {
             const R w = ray.m == 0 ? ds * (R)0.5 : ds;
-            scatter4(grad, M.nx, so.s1, scale * w * kap);
+            acc_add(grad, M.nx, acc, so.s1, scale * w * kap);
             nxt.m = ray.m + 1;
             ray = nxt;
             continue;
@@ -702,16 +765,246 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
             Sample<R> sq = lookup_at<R, COMP>(M, g, hit.qx, hit.qy);
             if (sq.c > (R)0) {
                 R wm = (R)(ray.m == 0 ? 0.5 * dsp : 0.5 * (g.ds + dsp));
-                scatter4(grad, M.nx, so.s1, scale * wm * kap);
+                acc_add(grad, M.nx, acc, so.s1, scale * wm * kap);
                 R icq = rcp(sq.c);
                 R kq = A.weight == RTX_W_DTDC ? -icq * icq : (R)1;
-                scatter4(grad, M.nx, sq, scale * (R)(0.5 * dsp) * kq);
+                acc_add(grad, M.nx, acc, sq, scale * (R)(0.5 * dsp) * kq);
             }
         }
+        acc_flush(grad, M.nx, acc);
         p += stride;
         next_pair();
     }
     block_sum2(n_steps, n_rays, A.stats);
+}
+
+// ------------------------------------------------------------ path weights --
+// Row i of the system matrix, W_ij = h sum_m w_m phi_j(p_m), is emitted in three
+// passes: count cell visits (4 entries each), fill the entries of every visit
+// into the row's segment of a scratch buffer, then sort + merge each row in LDS.
+struct WArgs {
+    const int32_t *pairs;
+    int64_t n_pairs;
+    const double *theta;
+    const int8_t *status;
+    int max_steps;
+    int64_t *rawcnt;        // count pass: entries per row
+    const int64_t *rawoff;  // fill pass: row offsets into cols/vals
+    int32_t *cols;
+    void *vals;
+};
+
+template <class R, bool FILL>
+struct RowSink {
+    int32_t n0;  // node index of the visited cell's lower-left corner, -1 = none
+    R a00, a10, a01, a11;
+    int64_t at, end;  // fill cursor and end of the row's segment
+    int64_t count;
+    int32_t *cols;
+    R *vals;
+    int nx;
+
+    __device__ __forceinline__ void put(int32_t c, R v)
+    {
+        if (at < end) {
+            cols[at] = c;
+            vals[at] = v;
+        }
+        at++;
+    }
+    __device__ __forceinline__ void flush()
+    {
+        if (n0 >= 0) {
+            if (FILL) {
+                put(n0, a00);
+                put(n0 + 1, a10);
+                put(n0 + nx, a01);
+                put(n0 + nx + 1, a11);
+            }
+            count += 4;
+        }
+        n0 = -1;
+        a00 = a10 = a01 = a11 = (R)0;
+    }
+    __device__ __forceinline__ void add(const Sample<R> &s, R a)
+    {
+        int32_t c = s.iy * nx + s.ix;
+        if (c != n0) {
+            flush();
+            n0 = c;
+        }
+        R omt = (R)1 - s.t, oms = (R)1 - s.s;
+        a00 = fma(a * omt, oms, a00);
+        a10 = fma(a * s.t, oms, a10);
+        a01 = fma(a * omt, s.s, a01);
+        a11 = fma(a * s.t, s.s, a11);
+    }
+};
+
+template <class R, bool COMP, int INTEG, bool FILL>
+__global__ void __launch_bounds__(kBlock) k_weights(Medium<R> M, Geo g, WArgs A)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const R ds = (R)g.ds;
+    const R R2 = (R)(g.R * g.R);
+    const R cx = (R)g.cx, cy = (R)g.cy;
+    const R hh = (R)g.h;
+    Ray<R> ray;
+    RowSink<R, FILL> sink;
+    sink.cols = A.cols;
+    sink.vals = (R *)A.vals;
+    sink.nx = M.nx;
+    bool active = false;
+    TraceArgs pa;
+    pa.pairs = A.pairs;
+
+    auto begin_row = [&]() {
+        sink.n0 = -1;
+        sink.a00 = sink.a10 = sink.a01 = sink.a11 = (R)0;
+        sink.count = 0;
+        if (FILL) {
+            sink.at = A.rawoff[p];
+            sink.end = A.rawoff[p] + A.rawcnt[p];
+        }
+    };
+    auto end_row = [&]() {
+        sink.flush();
+        if (!FILL) A.rawcnt[p] = sink.count;
+    };
+    auto next_pair = [&]() {
+        while (p < A.n_pairs) {
+            int e, r;
+            bool ok = pair_of(pa, g, p, e, r);
+            ok = ok && (A.status[p] == RTX_RAY_LINKED || A.status[p] == RTX_RAY_NOT_CONVERGED);
+            begin_row();
+            if (ok) {
+                start_ray<R, COMP>(ray, g, e, A.theta[p]);
+                active = true;
+                return;
+            }
+            end_row();
+            p += stride;
+        }
+        active = false;
+    };
+    next_pair();
+
+    while (active) {
+        Ray<R> nxt;
+        StepOut<R> so = ray_step<R, COMP, INTEG>(M, ray, nxt, ds);
+        const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
+        R pu = (nxt.uh - cx) + nxt.ul, pv = (nxt.vh - cy) + nxt.vl;
+        const bool crossed = !bad && (pu * pu + pv * pv >= R2);
+        const bool exhausted = !bad && !crossed && (ray.m + 1 >= A.max_steps);
+        if (!(bad || crossed || exhausted)) {
+            sink.add(so.s1, hh * (ray.m == 0 ? ds * (R)0.5 : ds));
+            nxt.m = ray.m + 1;
+            ray = nxt;
+            continue;
+        }
+        if (crossed) {
+            Hit hit = intersect<R>(g, ray, nxt);
+            double dsp = hit.t * g.ds;
+            Sample<R> sq = lookup_at<R, COMP>(M, g, hit.qx, hit.qy);
+            if (sq.c > (R)0) {
+                sink.add(so.s1, (R)(g.h * (ray.m == 0 ? 0.5 * dsp : 0.5 * (g.ds + dsp))));
+                sink.add(sq, (R)(g.h * 0.5 * dsp));
+            }
+        }
+        end_row();
+        p += stride;
+        next_pair();
+    }
+}
+
+// One block per row: the row's entries are sorted by node index in LDS
+// (bitonic), equal nodes are summed, zero sums dropped, and the merged row is
+// written back to the start of its segment; ucnt[row] = merged length.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_wmerge(const int64_t *__restrict__ rawoff,
+                                                   const int64_t *__restrict__ rawcnt, int32_t *cols, R *vals,
+                                                   int64_t *__restrict__ ucnt, int cap)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    R *val = (R *)smem;
+    int32_t *key = (int32_t *)(smem + (size_t)cap * sizeof(R));
+    __shared__ int part[kBlock];
+    const int64_t row = blockIdx.x;
+    const int n = (int)rawcnt[row];
+    const int64_t off = rawoff[row];
+    const int tid = threadIdx.x;
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int i = tid; i < np; i += blockDim.x) {
+        key[i] = i < n ? cols[off + i] : 0x7fffffff;
+        val[i] = i < n ? vals[off + i] : (R)0;
+    }
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < np; i += blockDim.x) {
+                int q = i ^ j;
+                if (q > i) {
+                    bool up = (i & k) == 0;
+                    int32_t a = key[i], b = key[q];
+                    if ((a > b) == up) {
+                        key[i] = b;
+                        key[q] = a;
+                        R t = val[i];
+                        val[i] = val[q];
+                        val[q] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // each thread owns a contiguous chunk; a head sums its run (which may run
+    // into the next chunk) and is kept if the sum is not zero
+    const int chunk = (np + blockDim.x - 1) / blockDim.x;
+    const int lo = tid * chunk, hi = min(n, lo + chunk);
+    int kept = 0;
+    for (int i = lo; i < hi; i++) {
+        if (i > 0 && key[i] == key[i - 1]) continue;
+        R sum = val[i];
+        for (int j = i + 1; j < n && key[j] == key[i]; j++) sum += val[j];
+        val[i] = sum;
+        kept += sum != (R)0;
+    }
+    part[tid] = kept;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        int v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int pos = part[tid] - kept;
+    for (int i = lo; i < hi; i++) {
+        if (i > 0 && key[i] == key[i - 1]) continue;
+        if (val[i] != (R)0) {
+            cols[off + pos] = key[i];
+            vals[off + pos] = val[i];
+            pos++;
+        }
+    }
+    if (tid == blockDim.x - 1) ucnt[row] = part[tid];
+}
+
+// Copies each merged row to its place in the caller's CSR arrays.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_wcompact(const int64_t *__restrict__ rawoff,
+                                                     const int64_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ cols, const R *__restrict__ vals,
+                                                     int32_t *__restrict__ w_col, R *__restrict__ w_val)
+{
+    const int64_t row = blockIdx.x;
+    const int64_t src = rawoff[row], dst = rowptr[row], n = rowptr[row + 1] - rowptr[row];
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        w_col[dst + i] = cols[src + i];
+        w_val[dst + i] = vals[src + i];
+    }
 }
 
 // Per pair: rho_i = sum_k w_k Im(exp(-i w_k T_i) r_ik), one wave per pair, lanes
@@ -763,6 +1056,8 @@ int check_opts(const rtx_grid *g, const rtx_ring *r, const rtx_opts *o)
     if (!g || !r || !o) return fail(RTX_E_ARG, "null grid/ring/opts");
     if (g->nx < 4 || g->ny < 4) return fail(RTX_E_ARG, "grid must be at least 4x4 (got %dx%d)", g->nx, g->ny);
     if (!(g->h > 0)) return fail(RTX_E_ARG, "grid spacing h must be > 0");
+    if ((int64_t)(g->nx - 1) * (g->ny - 1) >= (1 << 24))
+        return fail(RTX_E_ARG, "grid of %dx%d nodes exceeds 2^24 cells", g->nx, g->ny);
     if (r->n_elem < 2) return fail(RTX_E_ARG, "ring needs >= 2 elements");
     if (!(r->radius > 0)) return fail(RTX_E_ARG, "ring radius must be > 0");
     if (o->prec != RTX_F64 && o->prec != RTX_F32C) return fail(RTX_E_ARG, "unknown precision %d", o->prec);
@@ -857,6 +1152,99 @@ int launch_adjoint(rtx_plan_s *P, const AdjArgs &A, R *grad, hipStream_t s)
     return RTX_OK;
 }
 
+constexpr int kMergeCap = 8192;  // entries per row the LDS merge can sort
+
+// Device scratch of one weights call, freed on every exit path.
+struct Scratch {
+    std::vector<void *> ptrs;
+    ~Scratch()
+    {
+        for (void *q : ptrs) (void)hipFree(q);
+    }
+    template <class T>
+    T *get(size_t n)
+    {
+        void *q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(1, n) * sizeof(T)) != hipSuccess) return nullptr;
+        ptrs.push_back(q);
+        return (T *)q;
+    }
+};
+
+template <class R, bool COMP>
+int emit_weights(rtx_plan_s *P, const TraceArgs &T, int64_t *w_rowptr, int32_t *w_col, R *w_val, int64_t nnz_cap,
+                 hipStream_t s)
+{
+    const int64_t n = T.n_pairs;
+    Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
+    Geo g = make_geo(P);
+    Scratch S;
+    int64_t *rawcnt = S.get<int64_t>(n), *rawoff = S.get<int64_t>(n), *ucnt = S.get<int64_t>(n);
+    if (!rawcnt || !rawoff || !ucnt) return fail(RTX_E_NOMEM, "weights scratch");
+    WArgs A;
+    A.pairs = T.pairs;
+    A.n_pairs = n;
+    A.theta = T.theta;
+    A.status = T.status;
+    A.max_steps = T.max_steps;
+    A.rawcnt = rawcnt;
+    A.rawoff = rawoff;
+    A.cols = nullptr;
+    A.vals = nullptr;
+    auto kc = P->opts.integ == RTX_RK4 ? k_weights<R, COMP, 4, false> : k_weights<R, COMP, 2, false>;
+    auto kf = P->opts.integ == RTX_RK4 ? k_weights<R, COMP, 4, true> : k_weights<R, COMP, 2, true>;
+    hipLaunchKernelGGL(kc, dim3(grid_blocks(P, kc, n)), dim3(kBlock), 0, s, M, g, A);
+    HIP_TRY(hipGetLastError());
+    std::vector<int64_t> h(n), off(n);
+    HIP_TRY(hipMemcpyAsync(h.data(), rawcnt, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int64_t total = 0, mx = 0;
+    for (int64_t i = 0; i < n; i++) {
+        off[i] = total;
+        total += h[i];
+        mx = std::max(mx, h[i]);
+    }
+    if (mx > kMergeCap)
+        return fail(RTX_E_UNSUPPORTED, "a path-weight row has %lld raw entries, above the %d the row merge handles",
+                    (long long)mx, kMergeCap);
+    int32_t *cols = S.get<int32_t>(total);
+    R *vals = S.get<R>(total);
+    if (!cols || !vals) return fail(RTX_E_NOMEM, "weights scratch (%lld entries)", (long long)total);
+    HIP_TRY(hipMemcpyAsync(rawoff, off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+    A.cols = cols;
+    A.vals = vals;
+    hipLaunchKernelGGL(kf, dim3(grid_blocks(P, kf, n)), dim3(kBlock), 0, s, M, g, A);
+    HIP_TRY(hipGetLastError());
+    int cap = 256;
+    while (cap < mx) cap <<= 1;
+    size_t shmem = (size_t)cap * (sizeof(R) + sizeof(int32_t));
+    hipLaunchKernelGGL(k_wmerge<R>, dim3((unsigned)n), dim3(kBlock), shmem, s, rawoff, rawcnt, cols, vals, ucnt,
+                       cap);
+    HIP_TRY(hipGetLastError());
+    std::vector<int64_t> u(n), rp(n + 1);
+    HIP_TRY(hipMemcpyAsync(u.data(), ucnt, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    rp[0] = 0;
+    for (int64_t i = 0; i < n; i++) rp[i + 1] = rp[i] + u[i];
+    HIP_TRY(hipMemcpyAsync(w_rowptr, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    if (w_col) {
+        if (!w_val) return fail(RTX_E_ARG, "w_val is required with w_col");
+        if (rp[n] > nnz_cap) {
+            HIP_TRY(hipStreamSynchronize(s));
+            return fail(RTX_E_CAPACITY, "%lld path weights exceed nnz_cap %lld", (long long)rp[n],
+                        (long long)nnz_cap);
+        }
+        int64_t *rowptr_d = S.get<int64_t>(n + 1);
+        if (!rowptr_d) return fail(RTX_E_NOMEM, "weights scratch");
+        HIP_TRY(hipMemcpyAsync(rowptr_d, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_wcompact<R>, dim3((unsigned)n), dim3(kBlock), 0, s, rawoff, rowptr_d, cols, vals,
+                           w_col, w_val);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(s));  // host vectors and scratch die here
+    return RTX_OK;
+}
+
 int check_pairs(const rtx_plan_s *P, const int32_t *pairs, int64_t n)
 {
     if (n < 0) return fail(RTX_E_ARG, "n_pairs < 0");
@@ -945,9 +1333,17 @@ int rtx_trace_rays(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_
     if (!P) return fail(RTX_E_ARG, "null plan");
     int rc = check_pairs(P, pairs, n_pairs);
     if (rc) return rc;
+    if (n_pairs == 0) {
+        rc = pack(P, c, (hipStream_t)stream);
+        if (rc || !w_rowptr) return rc;
+        static const int64_t zero = 0;
+        HIP_TRY(hipMemcpyAsync(w_rowptr, &zero, sizeof zero, hipMemcpyHostToDevice, (hipStream_t)stream));
+        HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+        return RTX_OK;
+    }
     if (!theta || !status) return fail(RTX_E_ARG, "theta and status are required");
-    if (w_rowptr || w_col || w_val) return fail(RTX_E_UNSUPPORTED, "path-weight emission is not available");
-    (void)nnz_cap;
+    if (!w_rowptr && (w_col || w_val)) return fail(RTX_E_ARG, "w_col/w_val need w_rowptr");
+    if (w_col && nnz_cap < 0) return fail(RTX_E_ARG, "nnz_cap < 0");
     hipStream_t s = (hipStream_t)stream;
     rc = pack(P, c, s);
     if (rc) return rc;
@@ -966,8 +1362,14 @@ int rtx_trace_rays(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_
     A.tol = P->opts.tol_px;
     A.flags = P->opts.flags;
     A.stats = P->stats;
-    if (P->opts.prec == RTX_F32C) return launch_trace<float, true>(P, A, s);
-    return launch_trace<double, false>(P, A, s);
+    if (P->opts.prec == RTX_F32C) {
+        rc = launch_trace<float, true>(P, A, s);
+        if (rc || !w_rowptr) return rc;
+        return emit_weights<float, true>(P, A, w_rowptr, w_col, (float *)w_val, nnz_cap, s);
+    }
+    rc = launch_trace<double, false>(P, A, s);
+    if (rc || !w_rowptr) return rc;
+    return emit_weights<double, false>(P, A, w_rowptr, w_col, (double *)w_val, nnz_cap, s);
 }
 
 int rtx_tof_forward(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_pairs, double *theta,
@@ -985,7 +1387,9 @@ int rtx_tof_adjoint(rtx_plan P, const double *c, const int32_t *pairs, int64_t n
     if (!P) return fail(RTX_E_ARG, "null plan");
     int rc = check_pairs(P, pairs, n_pairs);
     if (rc) return rc;
-    if (!theta || !status || !resid || !grad) return fail(RTX_E_ARG, "theta, status, resid and grad are required");
+    if (!grad) return fail(RTX_E_ARG, "grad is required");
+    if (n_pairs == 0) return pack(P, c, (hipStream_t)stream);
+    if (!theta || !status || !resid) return fail(RTX_E_ARG, "theta, status and resid are required");
     if (weight != RTX_W_LENGTH && weight != RTX_W_DTDC) return fail(RTX_E_ARG, "unknown weight %d", weight);
     if (resid_kind != RTX_RESID_REAL && resid_kind != RTX_RESID_RAYBORN_C64)
         return fail(RTX_E_ARG, "unknown resid_kind %d", resid_kind);

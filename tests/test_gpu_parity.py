@@ -238,3 +238,57 @@ def test_fisheye_f64_linked_matches_closed_form(rtx):
     T = np.array([cf.fisheye_tof(pts[e], pts[r], 1500.0, 0.040) for e, r in synth.all_pairs(32)])
     assert np.max(np.abs(out["tof"] / T - 1)) < 5e-4
     assert math.isfinite(out["tof"].sum())
+
+
+def _dense_rows(rowptr, cols, vals, n_nodes):
+    rows = []
+    for i in range(len(rowptr) - 1):
+        r = np.zeros(n_nodes)
+        r[cols[rowptr[i]:rowptr[i + 1]]] = vals[rowptr[i]:rowptr[i + 1]]
+        rows.append(r)
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_path_weights_match_oracle(rtx, prec):
+    """System-matrix rows of the linked rays: node sets (bit-exact, sorted,
+    unique) and values against the oracle's rows at the same angles."""
+    n, h = 80, 0.5e-3
+    c = _gauss(n, h, seed=31)
+    ring = (20, 0.45 * n * h * 0.9, 0.0)
+    pairs = synth.all_pairs(20)
+    plan = rtx.Plan(n, n, h, *ring, prec=prec)
+    out = plan.trace(_dev(c), weights=True)
+    th = _np(out["theta"])
+    rp, col, val = _np(out["w_rowptr"]), _np(out["w_col"]), _np(out["w_val"]).astype(np.float64)
+    plan.close()
+    orp, ocol, oval = oracle.weights_csr(c, h, ring, pairs, th)
+    assert rp[0] == 0 and np.all(np.diff(rp) >= 0)
+    for i in range(len(pairs)):
+        cc = col[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(cc) > 0)
+    tol = 1e-12 if prec == "f64" else 2e-5
+    G, O = _dense_rows(rp, col, val, n * n), _dense_rows(orp, ocol, oval, n * n)
+    scale = O.max(axis=1, keepdims=True)
+    assert np.abs(G - O).max(axis=1).max() <= tol * scale.max()
+    if prec == "f64":
+        assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    else:  # entries may differ only where a weight is at rounding level
+        assert np.all(((G != 0) == (O != 0)) | (np.abs(G - O) <= tol * scale))
+    # rows sum to the path length
+    np.testing.assert_allclose(np.add.reduceat(val, rp[:-1]), _np(out["len"]), rtol=tol * 10)
+    # capacity error path
+    plan = rtx.Plan(n, n, h, *ring, prec=prec)
+    out2 = plan.trace(_dev(c))
+    with pytest.raises(rtx.RtxError):
+        import ctypes as C
+        from paper_2511_18511_amd import _binding as B
+        rowptr = torch.zeros(len(pairs) + 1, dtype=torch.int64, device=DEV)
+        colb = torch.empty(10, dtype=torch.int32, device=DEV)
+        valb = torch.empty(10, dtype=plan.real, device=DEV)
+        st = torch.empty(len(pairs), dtype=torch.int8, device=DEV)
+        plan._apply(B.RTX_FIXED_ANGLE)
+        B.rtx_trace_rays(plan._handle, None, None, len(pairs), C.c_void_p(out2["theta"].data_ptr()), None, None,
+                         None, None, C.c_void_p(st.data_ptr()), C.c_void_p(rowptr.data_ptr()),
+                         C.c_void_p(colb.data_ptr()), C.c_void_p(valb.data_ptr()), 10, C.c_void_p(0))
+    plan.close()
