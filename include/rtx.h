@@ -173,6 +173,53 @@ int rtx_tof_adjoint(rtx_plan plan, const double *c, const int32_t *pairs, int64_
    device): total RK steps marched and rays traced. */
 int rtx_plan_stats(rtx_plan plan, int64_t *trace_steps, int64_t *trace_rays, int64_t *adjoint_steps);
 
+/* Launch shape of the plan's persistent kernels: rays (threads) per block,
+   64, 128 or 256 (default 256).  Results do not depend on it; the autotuner
+   in the Python package picks it per workload. */
+int rtx_plan_set_launch(rtx_plan plan, int32_t rays_per_block);
+
+/* ---- batched independent instances (one launch graph) ---------------------
+   Many (medium, ring, pairs) problems traced by one persistent kernel over the
+   concatenated pair space, optionally followed by one adjoint kernel; the whole
+   run (counter reset, medium packing of every instance, trace, adjoint) is
+   captured into a HIP graph on the first rtx_batch_run and replayed after.
+   Every instance shares the batch's rtx_opts (precision, integrator, step,
+   tolerance, limits, flags).  All arrays are caller-owned device memory that
+   must stay valid for the batch's lifetime (the graph keeps the pointers). */
+typedef struct {
+    rtx_grid grid;
+    rtx_ring ring;
+    const double *c;        /* float64 [ny][nx] sound speed */
+    const int32_t *pairs;   /* int32 [n][2] or NULL = all ordered pairs */
+    int64_t n_pairs;        /* >= 1; n_elem (n_elem - 1) when pairs == NULL */
+    double *theta;          /* [n] in/out, as in rtx_trace_rays (required) */
+    double *tof, *len, *miss_px; /* [n] outputs (may be NULL) */
+    int32_t *n_marches;     /* [n] (may be NULL) */
+    int8_t *status;         /* [n] (required) */
+    const double *resid;    /* float64 [n] adjoint residual rho, or NULL (then for every instance) */
+    void *grad;             /* [ny][nx] float/double per precision, accumulated into (with resid) */
+} rtx_instance;
+
+typedef struct rtx_batch_s *rtx_batch;
+
+/* Validates every instance (as rtx_plan_create does), allocates the packed
+   tables and per-instance descriptors.  weight: rtx_weight of the adjoint.
+   rays_per_block: 0 (default 256), 64, 128 or 256.  inst is (host) [n_inst]. */
+int rtx_batch_create(rtx_batch *out, const rtx_opts *opts, int32_t weight, int32_t rays_per_block,
+                     int32_t n_inst, const rtx_instance *inst);
+
+/* Enqueues one run of the batch graph on stream. */
+int rtx_batch_run(rtx_batch batch, void *stream);
+
+/* Per-instance completion of the last run (synchronises the device), in ms from
+   the start of the run, from the device wall clock: fwd_ms when the instance's
+   last pair was linked, done_ms when its last adjoint ray finished (= fwd_ms
+   without adjoint).  Both (host) [n_inst], either may be NULL. */
+int rtx_batch_times(rtx_batch batch, double *fwd_ms, double *done_ms);
+
+/* Frees the batch (synchronises the device first). */
+int rtx_batch_destroy(rtx_batch batch);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *rtx_last_error(void);
 

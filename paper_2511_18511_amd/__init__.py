@@ -164,6 +164,83 @@ class Plan:
         """(trace steps, trace rays, adjoint steps) of the last calls."""
         return B.rtx_plan_stats(self._handle)
 
+    def set_launch(self, rays_per_block):
+        """Rays (threads) per block of the persistent kernels: 64, 128 or 256."""
+        B.rtx_plan_set_launch(self._handle, rays_per_block)
+        self.rays_per_block = int(rays_per_block)
+
+
+class Batch:
+    """Independent (medium, ring) problems traced together: one persistent trace
+    kernel over all pairs of all instances (+ one adjoint kernel when residuals
+    are given), captured once into a HIP graph and replayed by run().
+
+    instances: list of dicts with c (float64 [ny, nx] device), h, n_elem,
+    radius, phi0 (optional), and optionally resid (float64 [n_pairs] device).
+    Outputs per instance (device tensors, reused across runs): theta, tof, len,
+    miss_px, n_marches, status, and grad with resid."""
+
+    def __init__(self, instances, prec="f32c", integ="rk4", ds_px=0.25, tol_px=1e-3, max_marches=30,
+                 max_steps=0, weight="length", rays_per_block=256, warm=False):
+        self.prec = prec
+        self.real = torch.float32 if prec == "f32c" else torch.float64
+        self.opts = B.rtx_opts(PRECISIONS[prec], INTEGRATORS[integ], float(ds_px), float(tol_px), int(max_marches),
+                               int(max_steps), B.RTX_WARM_START if warm else 0)
+        self.inst = []
+        descs = []
+        for spec in instances:
+            c = spec["c"]
+            _dev_check(c, torch.float64, None, "c")
+            ny, nx = c.shape
+            n_elem = int(spec["n_elem"])
+            n = n_elem * (n_elem - 1)
+            dev = c.device
+            o = {
+                "c": c,
+                "theta": torch.zeros(n, dtype=torch.float64, device=dev) if spec.get("theta") is None
+                else spec["theta"].clone(),
+                "tof": torch.empty(n, dtype=torch.float64, device=dev),
+                "len": torch.empty(n, dtype=torch.float64, device=dev),
+                "miss_px": torch.empty(n, dtype=torch.float64, device=dev),
+                "n_marches": torch.empty(n, dtype=torch.int32, device=dev),
+                "status": torch.empty(n, dtype=torch.int8, device=dev),
+            }
+            if spec.get("resid") is not None:
+                _dev_check(spec["resid"], torch.float64, (n,), "resid")
+                o["resid"] = spec["resid"]
+                o["grad"] = torch.zeros(ny, nx, dtype=self.real, device=dev)
+            self.inst.append(o)
+            descs.append(B.rtx_instance(
+                B.rtx_grid(nx, ny, float(spec["h"])), B.rtx_ring(n_elem, float(spec["radius"]),
+                                                                 float(spec.get("phi0", 0.0))),
+                c.data_ptr(), None, n, o["theta"].data_ptr(), o["tof"].data_ptr(), o["len"].data_ptr(),
+                o["miss_px"].data_ptr(), o["n_marches"].data_ptr(), o["status"].data_ptr(),
+                o["resid"].data_ptr() if "resid" in o else None, o["grad"].data_ptr() if "grad" in o else None))
+        wcode = {"length": B.RTX_W_LENGTH, "dtdc": B.RTX_W_DTDC}[weight]
+        self._handle = B.rtx_batch_create(self.opts, wcode, rays_per_block, descs)
+        self.n_pairs = sum(int(o["tof"].numel()) for o in self.inst)
+
+    def run(self):
+        """Enqueues one run on the current stream (the adjoint accumulates into
+        each instance's grad: zero them first to get one run's gradient)."""
+        B.rtx_batch_run(self._handle, _stream())
+
+    def times(self):
+        """Per-instance completion of the last run, ms from its start:
+        (forward linked, forward + adjoint done)."""
+        return B.rtx_batch_times(self._handle, len(self.inst))
+
+    def close(self):
+        if getattr(self, "_handle", None):
+            B.rtx_batch_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 def trace_rays(c, h, n_elem, radius, phi0=0.0, pairs=None, theta=None, warm=False, fixed=False, **opts):
     """One-shot linked tracing of a float64 [ny, nx] device medium."""

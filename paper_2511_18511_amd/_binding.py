@@ -17,7 +17,8 @@ RTX_RAY_LINKED, RTX_RAY_NOT_CONVERGED, RTX_RAY_NO_HIT, RTX_RAY_BAD_INPUT = 0, 1,
 
 # every symbol include/rtx.h declares
 EXPORTS = ("rtx_plan_create", "rtx_plan_destroy", "rtx_plan_set_opts", "rtx_set_medium", "rtx_trace_rays",
-           "rtx_tof_forward", "rtx_tof_adjoint", "rtx_plan_stats", "rtx_last_error")
+           "rtx_tof_forward", "rtx_tof_adjoint", "rtx_plan_stats", "rtx_plan_set_launch", "rtx_batch_create",
+           "rtx_batch_run", "rtx_batch_times", "rtx_batch_destroy", "rtx_last_error")
 
 
 class rtx_grid(C.Structure):
@@ -31,6 +32,13 @@ class rtx_ring(C.Structure):
 class rtx_opts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("integ", C.c_int32), ("ds_px", C.c_double), ("tol_px", C.c_double),
                 ("max_marches", C.c_int32), ("max_steps", C.c_int32), ("flags", C.c_uint32)]
+
+
+class rtx_instance(C.Structure):
+    _fields_ = [("grid", rtx_grid), ("ring", rtx_ring), ("c", C.c_void_p), ("pairs", C.c_void_p),
+                ("n_pairs", C.c_int64), ("theta", C.c_void_p), ("tof", C.c_void_p), ("len", C.c_void_p),
+                ("miss_px", C.c_void_p), ("n_marches", C.c_void_p), ("status", C.c_void_p), ("resid", C.c_void_p),
+                ("grad", C.c_void_p)]
 
 
 class RtxError(RuntimeError):
@@ -60,6 +68,11 @@ def load():
     L.rtx_tof_forward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
     L.rtx_tof_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(C.c_double), i32, i32, vp, vp]
     L.rtx_plan_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.rtx_plan_set_launch.argtypes = [vp, i32]
+    L.rtx_batch_create.argtypes = [C.POINTER(vp), C.POINTER(rtx_opts), i32, i32, i32, C.POINTER(rtx_instance)]
+    L.rtx_batch_run.argtypes = [vp, vp]
+    L.rtx_batch_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.rtx_batch_destroy.argtypes = [vp]
     L.rtx_last_error.restype = C.c_char_p
     for name in EXPORTS:
         getattr(L, name).restype = C.c_char_p if name == "rtx_last_error" else C.c_int
@@ -114,3 +127,29 @@ def rtx_plan_stats(plan):
     a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
     check(load().rtx_plan_stats(plan, C.byref(a), C.byref(b), C.byref(c)))
     return a.value, b.value, c.value
+
+
+def rtx_plan_set_launch(plan, rays_per_block):
+    return check(load().rtx_plan_set_launch(plan, int(rays_per_block)))
+
+
+def rtx_batch_create(opts, weight, rays_per_block, instances):
+    arr = (rtx_instance * len(instances))(*instances)
+    h = C.c_void_p()
+    check(load().rtx_batch_create(C.byref(h), C.byref(opts), int(weight), int(rays_per_block), len(instances), arr))
+    return h
+
+
+def rtx_batch_run(batch, stream):
+    return check(load().rtx_batch_run(batch, stream))
+
+
+def rtx_batch_times(batch, n_inst):
+    f = (C.c_double * n_inst)()
+    d = (C.c_double * n_inst)()
+    check(load().rtx_batch_times(batch, f, d))
+    return list(f), list(d)
+
+
+def rtx_batch_destroy(batch):
+    return check(load().rtx_batch_destroy(batch))

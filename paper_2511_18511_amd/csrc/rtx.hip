@@ -535,15 +535,66 @@ __device__ void block_sum2(unsigned long long a, unsigned long long b, unsigned 
     }
 }
 
-template <class R, bool COMP, int INTEG>
-__global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs A)
+struct AdjArgs {
+    const int32_t *pairs;
+    int64_t n_pairs;
+    const double *theta;
+    const int8_t *status;
+    const double *rho;
+    int weight;
+    int max_steps;
+    unsigned long long *stats;
+};
+
+// One problem of a batch (device copy).
+template <class R>
+struct Inst {
+    Medium<R> M;
+    Geo g;
+    TraceArgs A;  // forward outputs and options
+    AdjArgs J;    // adjoint inputs
+    R *grad;      // adjoint output
+};
+
+// Batched instances: independent (medium, ring, outputs) problems traced by one
+// persistent launch over the concatenated pair space.  Lanes look up the
+// instance of each pair they take; per-instance counters record the wall clock
+// when an instance's last pair finishes.
+struct BatchArgs {
+    const void *inst;            // Inst<R>[n_inst] (device)
+    const int64_t *off;          // [n_inst + 1] prefix sums of the pair counts
+    int n_inst;
+    unsigned int *remain;        // [n_inst] pairs left, set before the launch
+    unsigned long long *t_done;  // [n_inst] wall clock at completion
+};
+
+__device__ __forceinline__ int find_inst(const BatchArgs &B, int64_t p)
+{
+    int lo = 0, hi = B.n_inst - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (B.off[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void mark_done(const BatchArgs &B, int k)
+{
+    if (atomicSub(B.remain + k, 1u) == 1u) B.t_done[k] = wall_clock64();
+}
+
+template <class R, bool COMP, int INTEG, bool BATCH>
+__global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs A, BatchArgs B)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool fixed = (A.flags & RTX_FIXED_ANGLE) != 0;
-    const R ds = (R)g.ds;
-    const R R2 = (R)(g.R * g.R);
-    const R cx = (R)g.cx, cy = (R)g.cy;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // item (pair of the launch)
+    int64_t n_items = BATCH ? B.off[B.n_inst] : A.n_pairs;
+    int64_t q = p;  // pair index within its instance
+    int k = 0;      // instance
+    Medium<R> m = M;
+    Geo gg = g;
+    TraceArgs a = A;
+    R ds = (R)gg.ds, R2 = (R)(gg.R * gg.R), cx = (R)gg.cx, cy = (R)gg.cy;
     unsigned long long n_steps = 0, n_rays = 0;
 
     Ray<R> ray;
@@ -554,17 +605,32 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
 
     // Takes pairs from p onward until one is valid (invalid ones are written).
     auto next_pair = [&]() {
-        while (p < A.n_pairs) {
-            if (pair_of(A, g, p, e, r)) {
-                pe = elem_angle(g, e);
-                dr = mod2pi(elem_angle(g, r) - pe);
-                double th0 = (A.flags & (RTX_WARM_START | RTX_FIXED_ANGLE)) ? A.theta[p] : (dr - kPi) / 2.0;
+        while (p < n_items) {
+            if (BATCH) {
+                k = find_inst(B, p);
+                const Inst<R> &I = ((const Inst<R> *)B.inst)[k];
+                m = I.M;
+                gg = I.g;
+                a = I.A;
+                q = p - B.off[k];
+                ds = (R)gg.ds;
+                R2 = (R)(gg.R * gg.R);
+                cx = (R)gg.cx;
+                cy = (R)gg.cy;
+            } else {
+                q = p;
+            }
+            if (pair_of(a, gg, q, e, r)) {
+                pe = elem_angle(gg, e);
+                dr = mod2pi(elem_angle(gg, r) - pe);
+                double th0 = (a.flags & (RTX_WARM_START | RTX_FIXED_ANGLE)) ? a.theta[q] : (dr - kPi) / 2.0;
                 link_reset(L, th0);
-                start_ray<R, COMP>(ray, g, e, th0);
+                start_ray<R, COMP>(ray, gg, e, th0);
                 active = true;
                 return;
             }
-            write_pair(A, p, A.theta[p], NAN, NAN, NAN, 0, RTX_RAY_BAD_INPUT);
+            write_pair(a, q, a.theta[q], NAN, NAN, NAN, 0, RTX_RAY_BAD_INPUT);
+            if (BATCH) mark_done(B, k);
             p += stride;
         }
         active = false;
@@ -573,13 +639,13 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
 
     while (active) {
         Ray<R> nxt;
-        StepOut<R> so = ray_step<R, COMP, INTEG>(M, ray, nxt, ds);
+        StepOut<R> so = ray_step<R, COMP, INTEG>(m, ray, nxt, ds);
         n_steps++;
         const R w_start = ray.m == 0 ? ds * (R)0.5 : ds;
         const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
         R pu = (nxt.uh - cx) + nxt.ul, pv = (nxt.vh - cy) + nxt.vl;
         const bool crossed = !bad && (pu * pu + pv * pv >= R2);
-        const bool exhausted = !bad && !crossed && (ray.m + 1 >= A.max_steps);
+        const bool exhausted = !bad && !crossed && (ray.m + 1 >= a.max_steps);
         if (!(bad || crossed || exhausted)) {
             add_T<R, COMP>(ray, w_start * so.ic1);
             nxt.Th = ray.Th;
@@ -596,60 +662,61 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
         if (bad) {
             st = RTX_RAY_BAD_INPUT;
         } else if (crossed) {
-            Hit hit = intersect<R>(g, ray, nxt);
-            double dsp = hit.t * g.ds;
-            Sample<R> sq = lookup_at<R, COMP>(M, g, hit.qx, hit.qy);
+            Hit hit = intersect<R>(gg, ray, nxt);
+            double dsp = hit.t * gg.ds;
+            Sample<R> sq = lookup_at<R, COMP>(m, gg, hit.qx, hit.qy);
             if (!(sq.c > (R)0)) {
                 st = RTX_RAY_BAD_INPUT;
             } else {
-                double wm = ray.m == 0 ? 0.5 * dsp : 0.5 * (g.ds + dsp);
+                double wm = ray.m == 0 ? 0.5 * dsp : 0.5 * (gg.ds + dsp);
                 double acc = ((double)ray.Th + (double)ray.Tl) + wm * (double)so.ic1 +
                              0.5 * dsp * (double)rcp(sq.c);
-                T = acc * g.h;
-                Lm = (ray.m * g.ds + dsp) * g.h;
+                T = acc * gg.h;
+                Lm = (ray.m * gg.ds + dsp) * gg.h;
                 g_mis = mod2pi(atan2(hit.qy, hit.qx) - pe) - dr;
                 st = RTX_RAY_LINKED;
             }
         }
         bool pair_done = false;
-        if (fixed) {
-            write_pair(A, p, L.th, T, Lm, fabs(g_mis) * g.R, 1, st);
+        if (a.flags & RTX_FIXED_ANGLE) {
+            write_pair(a, q, L.th, T, Lm, fabs(g_mis) * gg.R, 1, st);
             pair_done = true;
         } else if (st == RTX_RAY_BAD_INPUT) {
-            write_pair(A, p, L.th0, NAN, NAN, NAN, L.n_marches, RTX_RAY_BAD_INPUT);
+            write_pair(a, q, L.th0, NAN, NAN, NAN, L.n_marches, RTX_RAY_BAD_INPUT);
             pair_done = true;
         } else {
             double th_next;
             if (st == RTX_RAY_LINKED) {
-                double miss = fabs(g_mis) * g.R;
+                double miss = fabs(g_mis) * gg.R;
                 if (miss < L.best_miss) {
                     L.best_miss = miss;
                     L.best_th = L.th;
                     L.best_T = T;
                     L.best_L = Lm;
                 }
-                if (miss <= A.tol) {
-                    write_pair(A, p, L.th, T, Lm, miss, L.n_marches, RTX_RAY_LINKED);
+                if (miss <= a.tol) {
+                    write_pair(a, q, L.th, T, Lm, miss, L.n_marches, RTX_RAY_LINKED);
                     pair_done = true;
                 }
                 th_next = pair_done ? 0.0 : link_next_hit(L, g_mis);
             } else {
                 th_next = L.nvalid > 0 ? 0.5 * (L.th + L.thb) : 0.5 * L.th;
             }
-            if (!pair_done && L.n_marches >= A.max_marches) {
+            if (!pair_done && L.n_marches >= a.max_marches) {
                 if (L.best_miss < INFINITY)
-                    write_pair(A, p, L.best_th, L.best_T, L.best_L, L.best_miss, L.n_marches,
+                    write_pair(a, q, L.best_th, L.best_T, L.best_L, L.best_miss, L.n_marches,
                                RTX_RAY_NOT_CONVERGED);
                 else
-                    write_pair(A, p, L.th0, NAN, NAN, NAN, L.n_marches, RTX_RAY_NO_HIT);
+                    write_pair(a, q, L.th0, NAN, NAN, NAN, L.n_marches, RTX_RAY_NO_HIT);
                 pair_done = true;
             }
             if (!pair_done) {
                 L.th = th_next;
-                start_ray<R, COMP>(ray, g, e, th_next);
+                start_ray<R, COMP>(ray, gg, e, th_next);
             }
         }
         if (pair_done) {
+            if (BATCH) mark_done(B, k);
             p += stride;
             next_pair();
         }
@@ -658,16 +725,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
 }
 
 // ---------------------------------------------------------- adjoint kernel --
-struct AdjArgs {
-    const int32_t *pairs;
-    int64_t n_pairs;
-    const double *theta;
-    const int8_t *status;
-    const double *rho;
-    int weight;
-    int max_steps;
-    unsigned long long *stats;
-};
+
 
 // Pending hat weights of one cell visit.  Consecutive samples of a ray that
 // fall in the same cell add into registers; the four node atomics go out when
@@ -706,14 +764,19 @@ __device__ __forceinline__ void acc_add(R *grad, int nx, CellAcc<R> &A, const Sa
     A.a11 = fma(a * s.t, s.s, A.a11);
 }
 
-template <class R, bool COMP, int INTEG>
-__global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs A, R *__restrict__ grad)
+template <class R, bool COMP, int INTEG, bool BATCH>
+__global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs A, R *grad, BatchArgs B)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const R ds = (R)g.ds;
-    const R R2 = (R)(g.R * g.R);
-    const R cx = (R)g.cx, cy = (R)g.cy;
+    int64_t n_items = BATCH ? B.off[B.n_inst] : A.n_pairs;
+    int64_t q = p;
+    int k = 0;
+    Medium<R> m = M;
+    Geo gg = g;
+    AdjArgs a = A;
+    R *gr = grad;
+    R ds = (R)gg.ds, R2 = (R)(gg.R * gg.R), cx = (R)gg.cx, cy = (R)gg.cy;
     unsigned long long n_steps = 0, n_rays = 0;
     Ray<R> ray;
     CellAcc<R> acc;
@@ -721,21 +784,37 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
     acc.a00 = acc.a10 = acc.a01 = acc.a11 = (R)0;
     R scale = 0;  // rho h
     bool active = false;
-    TraceArgs pa;
-    pa.pairs = A.pairs;
 
     auto next_pair = [&]() {
-        while (p < A.n_pairs) {
+        while (p < n_items) {
+            if (BATCH) {
+                k = find_inst(B, p);
+                const Inst<R> &I = ((const Inst<R> *)B.inst)[k];
+                m = I.M;
+                gg = I.g;
+                a = I.J;
+                gr = I.grad;
+                q = p - B.off[k];
+                ds = (R)gg.ds;
+                R2 = (R)(gg.R * gg.R);
+                cx = (R)gg.cx;
+                cy = (R)gg.cy;
+            } else {
+                q = p;
+            }
             int e, r;
-            bool ok = pair_of(pa, g, p, e, r);
-            ok = ok && (A.status[p] == RTX_RAY_LINKED || A.status[p] == RTX_RAY_NOT_CONVERGED);
-            double rho = ok ? A.rho[p] : 0.0;
+            TraceArgs pa;
+            pa.pairs = a.pairs;
+            bool ok = pair_of(pa, gg, q, e, r);
+            ok = ok && (a.status[q] == RTX_RAY_LINKED || a.status[q] == RTX_RAY_NOT_CONVERGED);
+            double rho = ok ? a.rho[q] : 0.0;
             if (ok && rho != 0.0) {
-                start_ray<R, COMP>(ray, g, e, A.theta[p]);
-                scale = (R)(rho * g.h);
+                start_ray<R, COMP>(ray, gg, e, a.theta[q]);
+                scale = (R)(rho * gg.h);
                 active = true;
                 return;
             }
+            if (BATCH) mark_done(B, k);
             p += stride;
         }
         active = false;
@@ -744,38 +823,52 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
 
     while (active) {
         Ray<R> nxt;
-        StepOut<R> so = ray_step<R, COMP, INTEG>(M, ray, nxt, ds);
+        StepOut<R> so = ray_step<R, COMP, INTEG>(m, ray, nxt, ds);
         n_steps++;
-        const R kap = A.weight == RTX_W_DTDC ? -so.ic1 * so.ic1 : (R)1;
+        const R kap = a.weight == RTX_W_DTDC ? -so.ic1 * so.ic1 : (R)1;
         const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
         R pu = (nxt.uh - cx) + nxt.ul, pv = (nxt.vh - cy) + nxt.vl;
         const bool crossed = !bad && (pu * pu + pv * pv >= R2);
-        const bool exhausted = !bad && !crossed && (ray.m + 1 >= A.max_steps);
+        const bool exhausted = !bad && !crossed && (ray.m + 1 >= a.max_steps);
         if (!(bad || crossed || exhausted)) {
             const R w = ray.m == 0 ? ds * (R)0.5 : ds;
-            acc_add(grad, M.nx, acc, so.s1, scale * w * kap);
+            acc_add(gr, m.nx, acc, so.s1, scale * w * kap);
             nxt.m = ray.m + 1;
             ray = nxt;
             continue;
         }
         n_rays++;
         if (crossed) {
-            Hit hit = intersect<R>(g, ray, nxt);
-            double dsp = hit.t * g.ds;
-            Sample<R> sq = lookup_at<R, COMP>(M, g, hit.qx, hit.qy);
+            Hit hit = intersect<R>(gg, ray, nxt);
+            double dsp = hit.t * gg.ds;
+            Sample<R> sq = lookup_at<R, COMP>(m, gg, hit.qx, hit.qy);
             if (sq.c > (R)0) {
-                R wm = (R)(ray.m == 0 ? 0.5 * dsp : 0.5 * (g.ds + dsp));
-                acc_add(grad, M.nx, acc, so.s1, scale * wm * kap);
+                R wm = (R)(ray.m == 0 ? 0.5 * dsp : 0.5 * (gg.ds + dsp));
+                acc_add(gr, m.nx, acc, so.s1, scale * wm * kap);
                 R icq = rcp(sq.c);
-                R kq = A.weight == RTX_W_DTDC ? -icq * icq : (R)1;
-                acc_add(grad, M.nx, acc, sq, scale * (R)(0.5 * dsp) * kq);
+                R kq = a.weight == RTX_W_DTDC ? -icq * icq : (R)1;
+                acc_add(gr, m.nx, acc, sq, scale * (R)(0.5 * dsp) * kq);
             }
         }
-        acc_flush(grad, M.nx, acc);
+        acc_flush(gr, m.nx, acc);
+        if (BATCH) mark_done(B, k);
         p += stride;
         next_pair();
     }
     block_sum2(n_steps, n_rays, A.stats);
+}
+
+// Start of a batch run: per-instance pair counters and the start timestamp.
+__global__ void k_batch_reset(const int64_t *__restrict__ off, int n_inst, unsigned int *remain_fwd,
+                              unsigned int *remain_adj, unsigned long long *t0)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_inst) {
+        unsigned int n = (unsigned int)(off[k + 1] - off[k]);
+        remain_fwd[k] = n;
+        remain_adj[k] = n;
+    }
+    if (k == 0) *t0 = wall_clock64();
 }
 
 // ------------------------------------------------------------ path weights --
@@ -1045,6 +1138,28 @@ struct rtx_plan_s {
     double *omega = nullptr;   // [n_freq_cap]
     int n_freq_cap = 0;
     int n_cu = 0;
+    int block = kBlock;  // threads (rays) per block of the persistent kernels
+};
+
+struct rtx_batch_s {
+    rtx_opts opts;
+    int32_t weight;
+    int n_inst = 0;
+    int block = kBlock;
+    int n_cu = 0;
+    bool adjoint = false;
+    std::vector<rtx_instance> inst;
+    std::vector<size_t> tab_off;   // byte offset of each instance's packed table
+    void *tabs = nullptr;          // all packed tables
+    void *dinst = nullptr;         // Inst<R>[n_inst]
+    int64_t *off = nullptr;        // [n_inst + 1]
+    unsigned int *remain = nullptr;          // [2][n_inst]
+    unsigned long long *times = nullptr;     // [1 + 2 n_inst]: t0, fwd done, adjoint done
+    unsigned long long *stats = nullptr;     // [2][kMaxBlocks][2]
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t total_pairs = 0;
 };
 
 namespace {
@@ -1116,14 +1231,20 @@ int pack(rtx_plan_s *P, const double *c, hipStream_t s)
 // Persistent launch: no more blocks than can be resident at once (lanes take
 // further pairs with a fixed stride), and no more than the pairs need.
 template <class K>
-int grid_blocks(const rtx_plan_s *P, K kernel, int64_t n)
+int grid_blocks_for(int n_cu, int block, K kernel, int64_t n)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    int64_t want = (n + kBlock - 1) / kBlock;
-    int64_t cap = (int64_t)P->n_cu * per_cu;
+    int64_t want = (n + block - 1) / block;
+    int64_t cap = (int64_t)n_cu * per_cu;
     return (int)std::max<int64_t>(1, std::min<int64_t>({want, cap, (int64_t)kMaxBlocks}));
+}
+
+template <class K>
+int grid_blocks(const rtx_plan_s *P, K kernel, int64_t n)
+{
+    return grid_blocks_for(P->n_cu, P->block, kernel, n);
 }
 
 template <class R, bool COMP>
@@ -1131,10 +1252,11 @@ int launch_trace(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
 {
     Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
     Geo g = make_geo(P);
-    auto kern = P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4> : k_trace<R, COMP, 2>;
+    auto kern = P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false> : k_trace<R, COMP, 2, false>;
     int blocks = grid_blocks(P, kern, A.n_pairs);
     P->stat_blocks_trace = blocks;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, M, g, A);
+    BatchArgs B{};
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(P->block), 0, s, M, g, A, B);
     HIP_TRY(hipGetLastError());
     return RTX_OK;
 }
@@ -1144,10 +1266,11 @@ int launch_adjoint(rtx_plan_s *P, const AdjArgs &A, R *grad, hipStream_t s)
 {
     Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
     Geo g = make_geo(P);
-    auto kern = P->opts.integ == RTX_RK4 ? k_adjoint<R, COMP, 4> : k_adjoint<R, COMP, 2>;
+    auto kern = P->opts.integ == RTX_RK4 ? k_adjoint<R, COMP, 4, false> : k_adjoint<R, COMP, 2, false>;
     int blocks = grid_blocks(P, kern, A.n_pairs);
     P->stat_blocks_adj = blocks;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, M, g, A, grad);
+    BatchArgs B{};
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(P->block), 0, s, M, g, A, grad, B);
     HIP_TRY(hipGetLastError());
     return RTX_OK;
 }
@@ -1193,7 +1316,7 @@ int emit_weights(rtx_plan_s *P, const TraceArgs &T, int64_t *w_rowptr, int32_t *
     A.vals = nullptr;
     auto kc = P->opts.integ == RTX_RK4 ? k_weights<R, COMP, 4, false> : k_weights<R, COMP, 2, false>;
     auto kf = P->opts.integ == RTX_RK4 ? k_weights<R, COMP, 4, true> : k_weights<R, COMP, 2, true>;
-    hipLaunchKernelGGL(kc, dim3(grid_blocks(P, kc, n)), dim3(kBlock), 0, s, M, g, A);
+    hipLaunchKernelGGL(kc, dim3(grid_blocks(P, kc, n)), dim3(P->block), 0, s, M, g, A);
     HIP_TRY(hipGetLastError());
     std::vector<int64_t> h(n), off(n);
     HIP_TRY(hipMemcpyAsync(h.data(), rawcnt, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
@@ -1213,7 +1336,7 @@ int emit_weights(rtx_plan_s *P, const TraceArgs &T, int64_t *w_rowptr, int32_t *
     HIP_TRY(hipMemcpyAsync(rawoff, off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
     A.cols = cols;
     A.vals = vals;
-    hipLaunchKernelGGL(kf, dim3(grid_blocks(P, kf, n)), dim3(kBlock), 0, s, M, g, A);
+    hipLaunchKernelGGL(kf, dim3(grid_blocks(P, kf, n)), dim3(P->block), 0, s, M, g, A);
     HIP_TRY(hipGetLastError());
     int cap = 256;
     while (cap < mx) cap <<= 1;
@@ -1252,6 +1375,103 @@ int check_pairs(const rtx_plan_s *P, const int32_t *pairs, int64_t n)
                                       (long long)P->max_pairs);
     if (!pairs && n != 0 && n != (int64_t)P->ring.n_elem * (P->ring.n_elem - 1))
         return fail(RTX_E_ARG, "pairs == NULL requires n_pairs = n_elem (n_elem - 1)");
+    return RTX_OK;
+}
+
+Geo geo_of(const rtx_grid &gr, const rtx_ring &ri, const rtx_opts &o)
+{
+    Geo g;
+    g.nx = gr.nx;
+    g.ny = gr.ny;
+    g.n_elem = ri.n_elem;
+    g.cx = 0.5 * (gr.nx - 1);
+    g.cy = 0.5 * (gr.ny - 1);
+    g.R = ri.radius / gr.h;
+    g.phi0 = ri.phi0;
+    g.h = gr.h;
+    g.ds = o.ds_px;
+    return g;
+}
+
+int max_steps_for(const rtx_grid &gr, const rtx_ring &ri, const rtx_opts &o)
+{
+    if (o.max_steps > 0) return o.max_steps;
+    return (int)ceil(8.0 * (ri.radius / gr.h) / o.ds_px);
+}
+
+// Enqueues one batch run on s: reset, pack every medium, trace, adjoint.
+template <class R, bool COMP>
+int batch_enqueue(rtx_batch_s *Bt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3((Bt->n_inst + kBlock - 1) / kBlock), dim3(kBlock), 0, s, Bt->off,
+                       Bt->n_inst, Bt->remain, Bt->remain + Bt->n_inst, Bt->times);
+    HIP_TRY(hipGetLastError());
+    for (int k = 0; k < Bt->n_inst; k++) {
+        const rtx_instance &I = Bt->inst[k];
+        int64_t cells = (int64_t)(I.grid.nx - 1) * (I.grid.ny - 1);
+        hipLaunchKernelGGL(k_pack<R>, dim3((unsigned)((cells + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, I.c,
+                           I.grid.nx, I.grid.ny, (R *)((char *)Bt->tabs + Bt->tab_off[k]));
+        HIP_TRY(hipGetLastError());
+    }
+    BatchArgs B;
+    B.inst = Bt->dinst;
+    B.off = Bt->off;
+    B.n_inst = Bt->n_inst;
+    B.remain = Bt->remain;
+    B.t_done = Bt->times + 1;
+    Medium<R> M{nullptr, 0, 0};
+    Geo g{};
+    TraceArgs A{};
+    A.stats = Bt->stats;
+    auto kt = Bt->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, true> : k_trace<R, COMP, 2, true>;
+    int blocks = grid_blocks_for(Bt->n_cu, Bt->block, kt, Bt->total_pairs);
+    hipLaunchKernelGGL(kt, dim3(blocks), dim3(Bt->block), 0, s, M, g, A, B);
+    HIP_TRY(hipGetLastError());
+    if (Bt->adjoint) {
+        AdjArgs J{};
+        J.stats = Bt->stats + 2 * kMaxBlocks;
+        B.remain = Bt->remain + Bt->n_inst;
+        B.t_done = Bt->times + 1 + Bt->n_inst;
+        auto ka = Bt->opts.integ == RTX_RK4 ? k_adjoint<R, COMP, 4, true> : k_adjoint<R, COMP, 2, true>;
+        int ablocks = grid_blocks_for(Bt->n_cu, Bt->block, ka, Bt->total_pairs);
+        hipLaunchKernelGGL(ka, dim3(ablocks), dim3(Bt->block), 0, s, M, g, J, (R *)nullptr, B);
+        HIP_TRY(hipGetLastError());
+    }
+    return RTX_OK;
+}
+
+template <class R>
+int batch_upload(rtx_batch_s *Bt)
+{
+    std::vector<Inst<R>> h(Bt->n_inst);
+    for (int k = 0; k < Bt->n_inst; k++) {
+        const rtx_instance &I = Bt->inst[k];
+        Inst<R> &d = h[k];
+        memset(&d, 0, sizeof d);
+        d.M = Medium<R>{(const R *)((char *)Bt->tabs + Bt->tab_off[k]), I.grid.nx, I.grid.ny};
+        d.g = geo_of(I.grid, I.ring, Bt->opts);
+        d.A.pairs = I.pairs;
+        d.A.n_pairs = I.n_pairs;
+        d.A.theta = I.theta;
+        d.A.tof = I.tof;
+        d.A.len = I.len;
+        d.A.miss = I.miss_px;
+        d.A.n_marches = I.n_marches;
+        d.A.status = I.status;
+        d.A.max_marches = Bt->opts.max_marches;
+        d.A.max_steps = max_steps_for(I.grid, I.ring, Bt->opts);
+        d.A.tol = Bt->opts.tol_px;
+        d.A.flags = Bt->opts.flags;
+        d.J.pairs = I.pairs;
+        d.J.n_pairs = I.n_pairs;
+        d.J.theta = I.theta;
+        d.J.status = I.status;
+        d.J.rho = I.resid;
+        d.J.weight = Bt->weight;
+        d.J.max_steps = d.A.max_steps;
+        d.grad = (R *)I.grad;
+    }
+    HIP_TRY(hipMemcpy(Bt->dinst, h.data(), sizeof(Inst<R>) * Bt->n_inst, hipMemcpyHostToDevice));
     return RTX_OK;
 }
 
@@ -1451,6 +1671,144 @@ int rtx_plan_stats(rtx_plan P, int64_t *trace_steps, int64_t *trace_rays, int64_
     if (trace_steps) *trace_steps = (int64_t)ts;
     if (trace_rays) *trace_rays = (int64_t)tr;
     if (adjoint_steps) *adjoint_steps = (int64_t)as;
+    return RTX_OK;
+}
+
+int rtx_plan_set_launch(rtx_plan P, int32_t rays_per_block)
+{
+    g_last_error.clear();
+    if (!P) return fail(RTX_E_ARG, "null plan");
+    if (rays_per_block != 64 && rays_per_block != 128 && rays_per_block != 256)
+        return fail(RTX_E_ARG, "rays_per_block must be 64, 128 or 256 (got %d)", rays_per_block);
+    P->block = rays_per_block;
+    return RTX_OK;
+}
+
+int rtx_batch_create(rtx_batch *out, const rtx_opts *opts, int32_t weight, int32_t rays_per_block,
+                     int32_t n_inst, const rtx_instance *inst)
+{
+    g_last_error.clear();
+    if (!out) return fail(RTX_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!opts || !inst || n_inst < 1) return fail(RTX_E_ARG, "need opts and at least one instance");
+    if (weight != RTX_W_LENGTH && weight != RTX_W_DTDC) return fail(RTX_E_ARG, "unknown weight %d", weight);
+    if (rays_per_block == 0) rays_per_block = kBlock;
+    if (rays_per_block != 64 && rays_per_block != 128 && rays_per_block != 256)
+        return fail(RTX_E_ARG, "rays_per_block must be 64, 128 or 256");
+    int n_with_resid = 0;
+    for (int k = 0; k < n_inst; k++) {
+        const rtx_instance &I = inst[k];
+        int rc = check_opts(&I.grid, &I.ring, opts);
+        if (rc) return fail(rc, "instance %d: %s", k, g_last_error.c_str());
+        if (!I.c || !I.theta || !I.status) return fail(RTX_E_ARG, "instance %d: c, theta and status are required", k);
+        int64_t all = (int64_t)I.ring.n_elem * (I.ring.n_elem - 1);
+        if (I.n_pairs < 1 || (!I.pairs && I.n_pairs != all))
+            return fail(RTX_E_ARG, "instance %d: bad n_pairs %lld", k, (long long)I.n_pairs);
+        if ((int64_t)(I.grid.nx - 1) * (I.grid.ny - 1) >= (1 << 24))
+            return fail(RTX_E_ARG, "instance %d: grid exceeds 2^24 cells", k);
+        if (I.resid && !I.grad) return fail(RTX_E_ARG, "instance %d: resid needs grad", k);
+        n_with_resid += I.resid != nullptr;
+    }
+    if (n_with_resid != 0 && n_with_resid != n_inst)
+        return fail(RTX_E_ARG, "either every instance has an adjoint residual or none has");
+    rtx_batch_s *Bt = new rtx_batch_s();
+    Bt->opts = *opts;
+    Bt->weight = weight;
+    Bt->n_inst = n_inst;
+    Bt->block = rays_per_block;
+    Bt->adjoint = n_with_resid > 0;
+    Bt->inst.assign(inst, inst + n_inst);
+    size_t esz = opts->prec == RTX_F32C ? sizeof(float) : sizeof(double);
+    size_t bytes = 0;
+    std::vector<int64_t> off(n_inst + 1, 0);
+    for (int k = 0; k < n_inst; k++) {
+        Bt->tab_off.push_back(bytes);
+        bytes += ((size_t)(inst[k].grid.nx - 1) * (inst[k].grid.ny - 1) * kCoef * esz + 255) / 256 * 256;
+        off[k + 1] = off[k] + inst[k].n_pairs;
+    }
+    Bt->total_pairs = off[n_inst];
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete Bt;
+        return fail(RTX_E_HIP, "no HIP device");
+    }
+    Bt->n_cu = prop.multiProcessorCount;
+    size_t inst_bytes = opts->prec == RTX_F32C ? sizeof(Inst<float>) : sizeof(Inst<double>);
+    if (hipMalloc(&Bt->tabs, bytes) != hipSuccess || hipMalloc(&Bt->dinst, inst_bytes * n_inst) != hipSuccess ||
+        hipMalloc((void **)&Bt->off, sizeof(int64_t) * (n_inst + 1)) != hipSuccess ||
+        hipMalloc((void **)&Bt->remain, sizeof(unsigned int) * 2 * n_inst) != hipSuccess ||
+        hipMalloc((void **)&Bt->times, sizeof(unsigned long long) * (1 + 2 * n_inst)) != hipSuccess ||
+        hipMalloc((void **)&Bt->stats, sizeof(unsigned long long) * 4 * kMaxBlocks) != hipSuccess) {
+        rtx_batch_destroy(Bt);
+        return fail(RTX_E_NOMEM, "batch workspace");
+    }
+    int rc = RTX_OK;
+    if (hipMemcpy(Bt->off, off.data(), sizeof(int64_t) * (n_inst + 1), hipMemcpyHostToDevice) != hipSuccess)
+        rc = fail(RTX_E_HIP, "upload of instance offsets failed");
+    if (!rc) rc = opts->prec == RTX_F32C ? batch_upload<float>(Bt) : batch_upload<double>(Bt);
+    if (rc) {
+        rtx_batch_destroy(Bt);
+        return rc;
+    }
+    *out = Bt;
+    return RTX_OK;
+}
+
+int rtx_batch_run(rtx_batch Bt, void *stream)
+{
+    g_last_error.clear();
+    if (!Bt) return fail(RTX_E_ARG, "null batch");
+    hipStream_t s = (hipStream_t)stream;
+    if (!Bt->exec) {  // capture the whole run once into a graph
+        if (!Bt->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&Bt->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(Bt->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = Bt->opts.prec == RTX_F32C ? batch_enqueue<float, true>(Bt, Bt->cap_stream)
+                                           : batch_enqueue<double, false>(Bt, Bt->cap_stream);
+        hipGraph_t gph = nullptr;
+        hipError_t e = hipStreamEndCapture(Bt->cap_stream, &gph);
+        if (rc) {
+            if (gph) (void)hipGraphDestroy(gph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(RTX_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        Bt->graph = gph;
+        HIP_TRY(hipGraphInstantiate(&Bt->exec, Bt->graph, nullptr, nullptr, 0));
+    }
+    HIP_TRY(hipGraphLaunch(Bt->exec, s));
+    return RTX_OK;
+}
+
+int rtx_batch_times(rtx_batch Bt, double *fwd_ms, double *done_ms)
+{
+    g_last_error.clear();
+    if (!Bt) return fail(RTX_E_ARG, "null batch");
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<unsigned long long> t(1 + 2 * Bt->n_inst);
+    HIP_TRY(hipMemcpy(t.data(), Bt->times, sizeof(unsigned long long) * t.size(), hipMemcpyDeviceToHost));
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    double ms_per_tick = 1.0 / (double)khz;
+    for (int k = 0; k < Bt->n_inst; k++) {
+        if (fwd_ms) fwd_ms[k] = (double)(long long)(t[1 + k] - t[0]) * ms_per_tick;
+        if (done_ms)
+            done_ms[k] = (double)(long long)(t[1 + (Bt->adjoint ? Bt->n_inst : 0) + k] - t[0]) * ms_per_tick;
+    }
+    return RTX_OK;
+}
+
+int rtx_batch_destroy(rtx_batch Bt)
+{
+    if (!Bt) return RTX_OK;
+    (void)hipDeviceSynchronize();
+    if (Bt->exec) (void)hipGraphExecDestroy(Bt->exec);
+    if (Bt->graph) (void)hipGraphDestroy(Bt->graph);
+    if (Bt->cap_stream) (void)hipStreamDestroy(Bt->cap_stream);
+    for (void *q : {(void *)Bt->tabs, Bt->dinst, (void *)Bt->off, (void *)Bt->remain, (void *)Bt->times,
+                    (void *)Bt->stats})
+        if (q) (void)hipFree(q);
+    delete Bt;
     return RTX_OK;
 }
 

@@ -51,6 +51,7 @@ def test_struct_layouts_match_c():
     assert C.sizeof(B.rtx_grid) == 16 and B.rtx_grid.h.offset == 8
     assert C.sizeof(B.rtx_ring) == 24 and B.rtx_ring.radius.offset == 8
     assert C.sizeof(B.rtx_opts) == 40 and B.rtx_opts.flags.offset == 32
+    assert C.sizeof(B.rtx_instance) == 128 and B.rtx_instance.c.offset == 40 and B.rtx_instance.grad.offset == 120
 
 
 def test_no_cpu_fallback_in_product_path():
