@@ -4,7 +4,8 @@ elements on a 60 mm ring, 65,280 ordered pairs, RK4 at 0.25 px, 1e-3 px linking
 tolerance), FP32-compensated (headline) and plain FP64, on one GPU.
 
 One step = pack the medium (node gradient + cell coefficients) -> linked trace
-of every pair from straight-ray starts -> adjoint of the path weights for a
+of every pair (cold start seeded by each emitter's fan of straight rays; the
+plain straight-ray start is measured too) -> adjoint of the path weights for a
 residual r ~ N(0, (1e-4 s)^2).  Prints one JSON line.
 """
 import argparse
@@ -31,7 +32,7 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
-def run_gpu(prec, c_host, cfg, steps, warmup, resid_host):
+def run_gpu(prec, c_host, cfg, steps, warmup, resid_host, fan=True):
     import torch
 
     import paper_2511_18511_amd as rtx
@@ -42,48 +43,51 @@ def run_gpu(prec, c_host, cfg, steps, warmup, resid_host):
     plan = rtx.Plan(cfg["nx"], cfg["ny"], cfg["h"], cfg["n_elem"], cfg["radius"], cfg["phi0"], prec=prec,
                     integ=cfg["integ"], ds_px=cfg["ds_px"], tol_px=cfg["tol_px"], max_marches=cfg["max_marches"])
     n = plan.n_all
-    out = plan.trace(c)  # allocates the output tensors once
+    out = plan.trace(c, fan=fan)  # allocates the output tensors once
     grad = torch.zeros(cfg["ny"], cfg["nx"], dtype=plan.real, device=dev)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * steps)]
 
-    def step(k=None):
+    def step():
         plan.set_medium(c)
-        if k is not None:
-            ev[3 * k].record()
-        plan.trace(None, out=out)
-        if k is not None:
-            ev[3 * k + 1].record()
+        plan.trace(None, out=out, fan=fan)
         grad.zero_()
         plan.adjoint(out["theta"], out["status"], resid, weight="length", grad=grad)
-        if k is not None:
-            ev[3 * k + 2].record()
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    plan.timing(True)  # HIP events around every kernel, on its launch stream
     t0 = time.perf_counter()
-    for k in range(steps):
-        step(k)
+    for _ in range(steps):
+        step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    trace_ms = np.array([ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(steps)])
-    adj_ms = np.array([ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(steps)])
+    tm = plan.timings()
+    plan.timing(False)
     trace_steps, trace_rays, adj_steps = plan.stats()
+    link_region = 1 if fan else 0  # the dominant kernel: the linking pass
+    link_steps, link_rays = plan.region_stats(link_region)
+    avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in tm.items()}
     st = out["status"].cpu().numpy()
+    fwd_ms = avg["pack"] + avg["trace"] + avg["fan_seed"] + avg["fan_link"]
     res = {
         "prec": prec,
+        "linking_start": "fan" if fan else "straight",
         "wall_s": wall,
         "ms_per_step": 1e3 * wall / steps,
         "rays_per_s": n * steps / wall,
-        "trace_ms": float(np.median(trace_ms)),
-        "trace_ms_mean": float(trace_ms.mean()),
-        "adjoint_ms": float(np.median(adj_ms)),
-        "forward_rays_per_s": n / (float(trace_ms.mean()) * 1e-3),
+        "kernel_ms": avg,
+        "forward_ms": fwd_ms,
+        "adjoint_ms": avg["adjoint"],
+        "forward_rays_per_s": n / (fwd_ms * 1e-3),
+        "dominant_kernel": "linking pass (k_trace, fan-seeded)" if fan else "k_trace",
+        "dominant_ms": avg["fan_link"] if fan else avg["trace"],
+        "dominant_rk_steps": int(link_steps),
         "trace_rk_steps": int(trace_steps),
         "trace_rays": int(trace_rays),
         "adjoint_rk_steps": int(adj_steps),
         "linked_fraction": float(np.mean(st == rtx.RTX_RAY_LINKED)),
         "mean_marches": float(out["n_marches"].double().mean().item()),
+        "max_marches": int(out["n_marches"].max().item()),
     }
     plan.close()
     return res, out
@@ -125,6 +129,28 @@ def cpu_baseline(c, cfg, resid, max_seconds=30.0):
             f" pairs of the same workload, linked trace + adjoint, {wall:.1f} s wall"}
 
 
+def measured_traffic(_unused=None):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2511_18511_amd", "csrc", "rtx.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.json"))):
+        try:
+            d = json.load(open(path))
+        except ValueError:
+            continue
+        if d.get("source_sha256") != sha:
+            continue
+        for name, v in d.get("kernels", {}).items():
+            if name.startswith("k_trace<float, true, 4, false, true>"):  # the fan-seeded linking pass
+                return v["fetch_bytes"] + v["write_bytes"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,33 +158,48 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 256 MiB device-to-device copy (the reference kernel that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a profile)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path needs no cross-GPU exchange "
               "for the forward pass, see DESIGN.md for how it shards", file=sys.stderr)
         sys.exit(2)
 
+    if args.calibrate_copy:
+        import torch
+
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     cfg, c = synth.make_config(WORKLOAD)
     n_pairs = cfg["n_elem"] * (cfg["n_elem"] - 1)
     resid = synth.real_residual(n_pairs, cfg["resid_seed"], cfg["resid_std"])
 
-    f32, _ = run_gpu("f32c", c, cfg, args.steps, args.warmup, resid)
-    print(f"# f32c {f32['ms_per_step']:.3f} ms/step, trace {f32['trace_ms']:.3f} ms, adjoint "
-          f"{f32['adjoint_ms']:.3f} ms", file=sys.stderr, flush=True)
-    f64 = None
-    if not args.no_f64:
-        f64, _ = run_gpu("f64", c, cfg, args.steps, args.warmup, resid)
-        print(f"# f64 {f64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    runs = {}
+    for prec in ("f32c",) + (() if args.no_f64 else ("f64",)):
+        for fan in (True, False):
+            r, _ = run_gpu(prec, c, cfg, args.steps, args.warmup, resid, fan=fan)
+            runs[(prec, fan)] = r
+            print(f"# {prec} {r['linking_start']}: {r['ms_per_step']:.3f} ms/step, forward {r['forward_ms']:.3f} ms "
+                  f"(max {r['max_marches']} rays/pair), adjoint {r['adjoint_ms']:.3f} ms", file=sys.stderr, flush=True)
+    f32 = runs[("f32c", True)]
+    f64 = runs.get(("f64", True))
 
-    # roofline of the dominant kernel (the linked trace), per launch
-    t_s = f32["trace_ms_mean"] * 1e-3
-    flops = f32["trace_rk_steps"] * FLOPS_PER_STEP
+    # roofline of the dominant kernel (the linking pass), per launch
+    t_s = f32["dominant_ms"] * 1e-3
+    flops = f32["dominant_rk_steps"] * FLOPS_PER_STEP
     roof = {"bound": "alu", "achieved": flops / t_s / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": flops / t_s / 1e12 / PEAK_FP32_TFLOPS, "traffic": None}
-    gather = {"kernel": "k_trace<float>", "bytes_per_launch": f32["trace_rk_steps"] * GATHER_VALUES_PER_STEP * 4,
-              "achieved_GBs": f32["trace_rk_steps"] * GATHER_VALUES_PER_STEP * 4 / t_s / 1e9,
-              "vs_hbm_peak_frac": f32["trace_rk_steps"] * GATHER_VALUES_PER_STEP * 4 / t_s / 1e9 / PEAK_HBM_GBS}
+    gbytes = f32["dominant_rk_steps"] * GATHER_VALUES_PER_STEP * 4
+    gather = {"kernel": "k_trace<float> linking pass", "bytes_per_launch": gbytes,
+              "achieved_GBs": gbytes / t_s / 1e9, "vs_hbm_peak_frac": gbytes / t_s / 1e9 / PEAK_HBM_GBS}
 
+    roof["traffic"] = measured_traffic()
     cpu = None if args.no_cpu else cpu_baseline(c, cfg, resid)
     line = {
         "metric": "linked rays/s (ToF+path) and adjoint time; FP32-comp vs FP64 plain, same GPU",
@@ -175,13 +216,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "256x256 grid at 0.5 mm, 12 seeded Gaussian inclusions on 1500 m/s, 256-element "
                                "ring of radius 60 mm, all 65,280 ordered pairs, RK4 ds=0.25 px, linking tol 1e-3 px, "
-                               "cold straight-ray start, forward T+L then adjoint A^T r",
+                               "cold start (fan-seeded secant), forward T+L then adjoint A^T r",
                    "pairs": n_pairs, "grid": [cfg["ny"], cfg["nx"]], "ring_elements": cfg["n_elem"]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "f32c": f32,
         "f64": f64,
         "f32c_over_f64": (f32["rays_per_s"] / f64["rays_per_s"]) if f64 else None,
+        "straight_start": {p: runs[(p, False)] for p, fan in runs if not fan},
         "gather": gather,
     }
     print(json.dumps(line))

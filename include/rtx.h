@@ -75,7 +75,13 @@ enum rtx_precision {
 enum rtx_integrator { RTX_HEUN = 2, RTX_RK4 = 4 };
 enum rtx_flags {
     RTX_WARM_START = 1u,  /* start linking from the given theta */
-    RTX_FIXED_ANGLE = 2u  /* trace once at the given theta, no linking */
+    RTX_FIXED_ANGLE = 2u, /* trace once at the given theta, no linking */
+    RTX_FAN_START = 4u    /* cold start seeded from the emitter's fan of straight rays
+                             (all ordered pairs only, pairs == NULL): every pair's
+                             straight ray is traced first (its first traced ray);
+                             the nearest sign change of the misfit over rays of
+                             neighbouring receivers of the same emitter seeds the
+                             secant; the linking rules are unchanged */
 };
 enum rtx_weight { RTX_W_LENGTH = 0, RTX_W_DTDC = 1 };
 enum rtx_resid_kind { RTX_RESID_REAL = 0, RTX_RESID_RAYBORN_C64 = 1 };
@@ -170,8 +176,24 @@ int rtx_tof_adjoint(rtx_plan plan, const double *c, const int32_t *pairs, int64_
                     void *stream);
 
 /* Work counters of the last trace / adjoint call on this plan (synchronises the
-   device): total RK steps marched and rays traced. */
+   device): total RK steps marched and rays traced (both trace passes of a fan
+   start), and adjoint steps. */
 int rtx_plan_stats(rtx_plan plan, int64_t *trace_steps, int64_t *trace_rays, int64_t *adjoint_steps);
+
+/* Work counters of one kernel launch of the last call: region 0 = the trace
+   kernel (the fixed straight-ray pass under RTX_FAN_START), 1 = the linking pass
+   of a fan start, 2 = the adjoint. */
+int rtx_plan_region_stats(rtx_plan plan, int32_t region, int64_t *steps, int64_t *rays);
+
+/* Per-kernel timing: while enabled, every kernel the plan launches is bracketed
+   by HIP events recorded on its launch stream.  rtx_plan_timing(plan, 1) starts
+   (and resets) it, 0 stops it; rtx_plan_timings (synchronises the device)
+   returns per slot (host arrays of RTX_NUM_SLOTS) the summed milliseconds and
+   the number of launches since the reset. */
+enum rtx_slot { RTX_SLOT_PACK = 0, RTX_SLOT_TRACE = 1, RTX_SLOT_FAN_SEED = 2, RTX_SLOT_FAN_LINK = 3,
+                RTX_SLOT_ADJOINT = 4, RTX_NUM_SLOTS = 5 };
+int rtx_plan_timing(rtx_plan plan, int32_t enable);
+int rtx_plan_timings(rtx_plan plan, double *total_ms, int32_t *count);
 
 /* Launch shape of the plan's persistent kernels: rays (threads) per block,
    64, 128 or 256 (default 256).  Results do not depend on it; the autotuner

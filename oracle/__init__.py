@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "oracle_rt.c")
 _LIB = os.path.join(_HERE, "liboracle_rt.so")
 
 LINKED, NOT_CONVERGED, NO_HIT, BAD_INPUT = 0, 1, 2, 3
-WARM, FIXED = 1, 2
+WARM, FIXED, FAN = 1, 2, 4
 HEUN, RK4 = 2, 4
 LENGTH, DTDC = 0, 1
 
@@ -153,10 +153,11 @@ def _integ_code(integ):
 
 
 def trace(medium, ring, pairs, theta=None, integ="rk4", ds_px=0.25, tol_px=1e-3, max_marches=30,
-          max_steps=0, fixed=False, warm=False):
+          max_steps=0, fixed=False, warm=False, fan=False):
     """Linked (or fixed-angle) tracing of pairs [n, 2] = (emitter, receiver).
 
-    ring = (n_elem, radius_m, phi0).  Returns a dict of numpy arrays:
+    ring = (n_elem, radius_m, phi0).  fan=True: fan start (needs all ordered
+    pairs in canonical order).  Returns a dict of numpy arrays:
     theta, tof (s), len (m), miss_px, n_marches, status."""
     args, keep = _medium_args(medium)
     n_elem, radius, phi0 = ring
@@ -166,7 +167,7 @@ def trace(medium, ring, pairs, theta=None, integ="rk4", ds_px=0.25, tol_px=1e-3,
     T, L, miss = np.empty(n), np.empty(n), np.empty(n)
     nm = np.empty(n, dtype=np.int32)
     st = np.empty(n, dtype=np.int8)
-    flags = (FIXED if fixed else 0) | (WARM if warm else 0)
+    flags = (FIXED if fixed else 0) | (WARM if warm else 0) | (FAN if fan else 0)
     rc = lib().or_trace(*args, int(n_elem), float(radius), float(phi0), _integ_code(integ), float(ds_px),
                         float(tol_px), int(max_marches), int(max_steps), flags, n, _i(pairs), _d(th), _d(T),
                         _d(L), _d(miss), _i(nm), _b(st))

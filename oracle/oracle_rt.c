@@ -52,6 +52,7 @@
 
 #define OPT_WARM 1
 #define OPT_FIXED 2
+#define OPT_FAN 4
 
 static const double PI = 3.14159265358979323846;
 
@@ -388,33 +389,96 @@ static int trace_at(const Medium *m, const Ring *ring, const Opts *o, int e, int
  *   (d) the limits +-pi/2 are never assumed to have a known misfit sign.
  * Stops when miss = |g| R <= tol (LINKED) or after max_marches traced rays
  * (NOT_CONVERGED, returning the traced ray of smallest miss). */
-static void link_pair(const Medium *m, const Ring *ring, const Opts *o, int e, int rcv, double theta0, LinkOut *out)
+typedef struct {
+    double th0; /* start angle, returned when no ray hits */
+    double tha, ga, thb, gb, th_neg, th_pos;
+    int nvalid, have_neg, have_pos;
+    double best_miss, best_th, best_T, best_L;
+} LinkState;
+
+static void link_init(LinkState *s, double th0)
+{
+    memset(s, 0, sizeof(*s));
+    s->th0 = th0;
+    s->best_miss = INFINITY;
+    s->best_th = th0;
+    s->best_T = s->best_L = NAN;
+}
+
+/* Next angle after a ray at th that hit with misfit g (secant step + (a), (b)). */
+static double link_after_hit(LinkState *s, double th, double g)
 {
     const double lim = PI / 2.0 - 1e-6;
-    double th = theta0;
-    double tha = 0, ga = 0, thb = 0, gb = 0;
-    int nvalid = 0, have_neg = 0, have_pos = 0;
-    double th_neg = 0, th_pos = 0;
-    double best_miss = INFINITY, best_th = theta0, best_T = NAN, best_L = NAN;
-    int any_bad = 0;
-    out->n_marches = 0;
-    for (int k = 0; k < o->max_marches; k++) {
+    double th_next;
+    if (g < 0) {
+        s->have_neg = 1;
+        s->th_neg = th;
+    }
+    if (g > 0) {
+        s->have_pos = 1;
+        s->th_pos = th;
+    }
+    s->tha = s->thb;
+    s->ga = s->gb;
+    s->thb = th;
+    s->gb = g;
+    s->nvalid++;
+    int den_zero = 0;
+    if (s->nvalid == 1) {
+        th_next = th - g / 2.0;
+    } else if (s->gb - s->ga == 0.0) {
+        den_zero = 1;
+        th_next = th - g / 2.0;
+    } else {
+        th_next = s->thb - s->gb * (s->thb - s->tha) / (s->gb - s->ga);
+    }
+    if (s->have_neg && s->have_pos) {
+        double lo = s->th_neg < s->th_pos ? s->th_neg : s->th_pos;
+        double hi = s->th_neg < s->th_pos ? s->th_pos : s->th_neg;
+        if (den_zero || !(th_next > lo && th_next < hi)) th_next = 0.5 * (s->th_neg + s->th_pos);
+    } else {
+        if (!(th_next < lim) && th_next == th_next) th_next = 0.5 * (th + lim);
+        if (!(th_next > -lim) && th_next == th_next) th_next = 0.5 * (th - lim);
+        if (!(th_next == th_next)) th_next = 0.5 * th;
+    }
+    return th_next;
+}
+
+/* Next angle after a ray at th that never reached the ring (c). */
+static double link_after_miss(const LinkState *s, double th)
+{
+    return (s->nvalid > 0) ? 0.5 * (th + s->thb) : 0.5 * th;
+}
+
+static void link_best(LinkState *s, double th, double miss, double T, double L)
+{
+    if (miss < s->best_miss) {
+        s->best_miss = miss;
+        s->best_th = th;
+        s->best_T = T;
+        s->best_L = L;
+    }
+}
+
+/* Runs the linking loop from angle th with state s and `done` rays already
+   traced for this pair. */
+static void link_run(const Medium *m, const Ring *ring, const Opts *o, int e, int rcv, LinkState *s, double th,
+                     int done, LinkOut *out)
+{
+    out->n_marches = done;
+    for (int k = done; k < o->max_marches; k++) {
         double g, T, L;
         int st = trace_at(m, ring, o, e, rcv, th, &g, &T, &L, NULL);
         out->n_marches++;
-        double th_next;
         if (st == ST_BAD_INPUT) {
-            any_bad = 1;
-            break;
+            out->theta = s->th0;
+            out->T = out->L = out->miss = NAN;
+            out->status = ST_BAD_INPUT;
+            return;
         }
         if (st == ST_LINKED) {
             double miss = fabs(g) * ring->radius_px;
-            if (miss < best_miss) {
-                best_miss = miss;
-                best_th = th;
-                best_T = T;
-                best_L = L;
-            }
+            link_best(s, th, miss, T, L);
             if (miss <= o->tol) {
                 out->theta = th;
                 out->T = T;
@@ -423,63 +487,118 @@ static void link_pair(const Medium *m, const Ring *ring, const Opts *o, int e, i
                 out->status = ST_LINKED;
                 return;
             }
-            if (g < 0) {
-                have_neg = 1;
-                th_neg = th;
-            }
-            if (g > 0) {
-                have_pos = 1;
-                th_pos = th;
-            }
-            tha = thb;
-            ga = gb;
-            thb = th;
-            gb = g;
-            nvalid++;
-            int den_zero = 0;
-            if (nvalid == 1) {
-                th_next = th - g / 2.0;
-            } else if (gb - ga == 0.0) {
-                den_zero = 1;
-                th_next = th - g / 2.0;
-            } else {
-                th_next = thb - gb * (thb - tha) / (gb - ga);
-            }
-            if (have_neg && have_pos) {
-                double lo = th_neg < th_pos ? th_neg : th_pos;
-                double hi = th_neg < th_pos ? th_pos : th_neg;
-                if (den_zero || !(th_next > lo && th_next < hi)) th_next = 0.5 * (th_neg + th_pos);
-            } else {
-                if (!(th_next < lim) && th_next == th_next) th_next = 0.5 * (th + lim);
-                if (!(th_next > -lim) && th_next == th_next) th_next = 0.5 * (th - lim);
-                if (!(th_next == th_next)) th_next = 0.5 * th;
-            }
-        } else { /* no interception: back off toward the latest angle that hit */
-            th_next = (nvalid > 0) ? 0.5 * (th + thb) : 0.5 * th;
+            th = link_after_hit(s, th, g);
+        } else {
+            th = link_after_miss(s, th);
         }
-        th = th_next;
     }
-    if (any_bad) {
-        out->theta = theta0;
-        out->T = NAN;
-        out->L = NAN;
-        out->miss = NAN;
+    if (s->best_miss < INFINITY) {
+        out->theta = s->best_th;
+        out->T = s->best_T;
+        out->L = s->best_L;
+        out->miss = s->best_miss;
+        out->status = ST_NOT_CONVERGED;
+    } else {
+        out->theta = s->th0;
+        out->T = out->L = out->miss = NAN;
+        out->status = ST_NO_HIT;
+    }
+}
+
+static void link_pair(const Medium *m, const Ring *ring, const Opts *o, int e, int rcv, double theta0, LinkOut *out)
+{
+    LinkState s;
+    link_init(&s, theta0);
+    link_run(m, ring, o, e, rcv, &s, theta0, 0, out);
+}
+
+/* Fan start (an initial-guess option; the secant and its safeguards are
+ * unchanged).  The straight-ray rays of all receivers of one emitter sample the
+ * same function: the hit angle H(theta) = mod(phi_hit - phi_e, 2 pi) of a ray
+ * launched at theta.  For receiver r with target D_r = mod(phi_r - phi_e, 2 pi)
+ * the samples give G_j = H_j - D_r at the straight angles theta_j of the
+ * receivers at offsets j = 1..n-1 (increasing in j).  The linking of r starts
+ * from its own straight ray (counted as its first traced ray):
+ *   - if that ray already links, it is the result;
+ *   - else, the sign change of G over consecutive samples (j, j+1) nearest to
+ *     r's own offset (searching j = own, own+1, own-1-1, ... outward) seeds the
+ *     secant: the end with the larger |G| then the one with the smaller |G| are
+ *     fed to the state machine as hitting rays, whose next angle is their
+ *     secant (linear) interpolation inside the bracket they form;
+ *   - with no such bracket, the own ray is fed alone (homogeneous Newton
+ *     second point), or, if it did not hit, the trapped-ray back-off applies.
+ * Only rays traced for this pair enter its best-ray record. */
+typedef struct {
+    double g, T, L; /* own straight ray: misfit (own receiver), time, length */
+    int st;
+} FanSample;
+
+static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, int rcv, const FanSample *row,
+                     LinkOut *out)
+{
+    const int n = ring->n_elem;
+    const int jr = ((rcv - e) % n + n) % n; /* own offset, 1..n-1 */
+    double pe = elem_angle(ring, e);
+    double Dr = mod2pi(elem_angle(ring, rcv) - pe);
+    double th_own = straight_angle(ring, e, rcv);
+    const FanSample *own = &row[jr - 1];
+    if (own->st == ST_BAD_INPUT) {
+        out->theta = th_own;
+        out->T = out->L = out->miss = NAN;
+        out->n_marches = 1;
         out->status = ST_BAD_INPUT;
         return;
     }
-    if (best_miss < INFINITY) {
-        out->theta = best_th;
-        out->T = best_T;
-        out->L = best_L;
-        out->miss = best_miss;
-        out->status = ST_NOT_CONVERGED;
-    } else {
-        out->theta = theta0;
-        out->T = NAN;
-        out->L = NAN;
-        out->miss = NAN;
-        out->status = ST_NO_HIT;
+    LinkState s;
+    link_init(&s, th_own);
+    if (own->st == ST_LINKED) {
+        double miss = fabs(own->g) * ring->radius_px;
+        link_best(&s, th_own, miss, own->T, own->L);
+        if (miss <= o->tol) {
+            out->theta = th_own;
+            out->T = own->T;
+            out->L = own->L;
+            out->miss = miss;
+            out->n_marches = 1;
+            out->status = ST_LINKED;
+            return;
+        }
     }
+    /* G_j relative to this receiver, NaN where the sample did not hit */
+    double *G = (double *)malloc(sizeof(double) * (n - 1));
+    double *TH = (double *)malloc(sizeof(double) * (n - 1));
+    for (int j = 1; j < n; j++) {
+        int k = (e + j) % n;
+        double Dj = mod2pi(elem_angle(ring, k) - pe);
+        G[j - 1] = row[j - 1].st == ST_LINKED ? (row[j - 1].g + Dj) - Dr : NAN;
+        TH[j - 1] = straight_angle(ring, e, k);
+    }
+    int found = -1;
+    for (int d = 0; d < n && found < 0; d++) {
+        int cand[2] = {jr - 1 + d, jr - 1 - d - 1};
+        for (int c = 0; c < 2; c++) {
+            int a = cand[c];
+            if (a < 0 || a + 1 > n - 2) continue;
+            if (G[a] == G[a] && G[a + 1] == G[a + 1] && G[a] * G[a + 1] <= 0.0) {
+                found = a;
+                break;
+            }
+        }
+    }
+    double th;
+    if (found >= 0) {
+        int near = fabs(G[found]) <= fabs(G[found + 1]) ? found : found + 1;
+        int far = near == found ? found + 1 : found;
+        link_after_hit(&s, TH[far], G[far]);
+        th = link_after_hit(&s, TH[near], G[near]);
+    } else if (own->st == ST_LINKED) {
+        th = link_after_hit(&s, th_own, own->g);
+    } else {
+        th = link_after_miss(&s, th_own);
+    }
+    free(G);
+    free(TH);
+    link_run(m, ring, o, e, rcv, &s, th, 1, out);
 }
 
 /* --------------------------------------------------------------- exported -- */
@@ -523,7 +642,9 @@ static void teardown(Medium *m)
    flags & OPT_FIXED: trace once at the given theta, no linking (status LINKED
    means "hit the ring"; miss is then the miss of that ray).
    flags & OPT_WARM: start linking from the given theta instead of the straight
-   ray.  Pairs with e == r or an index outside [0, n_elem) get ST_BAD_INPUT. */
+   ray.  flags & OPT_FAN: fan start (see link_fan); needs every ordered pair in
+   canonical order (returns -2 otherwise).  Pairs with e == r or an index outside
+   [0, n_elem) get ST_BAD_INPUT. */
 int or_trace(int kind, int nx, int ny, double h, const double *c, const double *mpar, int n_elem,
              double radius, double phi0, int integ, double ds_px, double tol_px, int max_marches,
              int max_steps, int flags, int n_pairs, const int32_t *pairs, double *theta, double *T,
@@ -535,6 +656,44 @@ int or_trace(int kind, int nx, int ny, double h, const double *c, const double *
     if (setup(kind, nx, ny, h, c, mpar, n_elem, radius, phi0, integ, ds_px, tol_px, max_marches, max_steps,
               flags, &m, &ring, &o))
         return -1;
+    if (flags & OPT_FAN) {
+        /* all ordered pairs in canonical order: row e holds receivers e+1..e+n-1 */
+        int n = n_elem;
+        if (n_pairs != n * (n - 1)) {
+            teardown(&m);
+            return -2;
+        }
+        for (int i = 0; i < n_pairs; i++) {
+            int e = i / (n - 1), k = i % (n - 1);
+            if (pairs[2 * i] != e || pairs[2 * i + 1] != (k < e ? k : k + 1)) {
+                teardown(&m);
+                return -2;
+            }
+        }
+        FanSample *row = (FanSample *)malloc(sizeof(FanSample) * (n - 1));
+        for (int e = 0; e < n; e++) {
+            for (int j = 1; j < n; j++) { /* straight rays of emitter e, by offset */
+                int k = (e + j) % n;
+                FanSample *f = &row[j - 1];
+                f->st = trace_at(&m, &ring, &o, e, k, straight_angle(&ring, e, k), &f->g, &f->T, &f->L, NULL);
+            }
+            for (int j = 1; j < n; j++) {
+                int r = (e + j) % n;
+                int i = e * (n - 1) + (r < e ? r : r - 1);
+                LinkOut lo;
+                link_fan(&m, &ring, &o, e, r, row, &lo);
+                theta[i] = lo.theta;
+                T[i] = lo.T;
+                L[i] = lo.L;
+                miss[i] = lo.miss;
+                n_marches[i] = lo.n_marches;
+                status[i] = (int8_t)lo.status;
+            }
+        }
+        free(row);
+        teardown(&m);
+        return 0;
+    }
     for (int i = 0; i < n_pairs; i++) {
         int e = pairs[2 * i], r = pairs[2 * i + 1];
         if (e == r || e < 0 || r < 0 || e >= n_elem || r >= n_elem) {

@@ -84,11 +84,13 @@ class Plan:
         _dev_check(pairs, torch.int32, None, "pairs")
         return pairs, pairs.shape[0]
 
-    def trace(self, c=None, pairs=None, theta=None, warm=False, fixed=False, out=None, weights=False, **over):
+    def trace(self, c=None, pairs=None, theta=None, warm=False, fixed=False, out=None, weights=False, fan=False,
+              **over):
         """Linked (or fixed-angle) tracing.  Returns a dict of device tensors:
         theta, tof (s), len (m), miss_px, n_marches, status, and with
         weights=True the system matrix of the traced rays (w_rowptr, w_col,
-        w_val; see weights())."""
+        w_val; see weights()).  fan=True: cold start seeded from each emitter's
+        fan of straight rays (all ordered pairs only)."""
         if c is not None:
             _dev_check(c, torch.float64, (self.ny, self.nx), "c")
         pairs, n = self._pairs(pairs)
@@ -104,7 +106,8 @@ class Plan:
             }
         if theta is not None:
             out["theta"].copy_(theta)
-        flags = (B.RTX_WARM_START if warm else 0) | (B.RTX_FIXED_ANGLE if fixed else 0)
+        flags = (B.RTX_WARM_START if warm else 0) | (B.RTX_FIXED_ANGLE if fixed else 0) | \
+            (B.RTX_FAN_START if fan else 0)
         self._apply(flags, **over)
         B.rtx_trace_rays(self._handle, _ptr(c), _ptr(pairs), n, _ptr(out["theta"]), _ptr(out.get("tof")),
                          _ptr(out.get("len")), _ptr(out.get("miss_px")), _ptr(out.get("n_marches")),
@@ -163,6 +166,22 @@ class Plan:
     def stats(self):
         """(trace steps, trace rays, adjoint steps) of the last calls."""
         return B.rtx_plan_stats(self._handle)
+
+    def region_stats(self, region):
+        """(steps, rays) of one kernel of the last call: 0 = trace (the fixed
+        straight pass under a fan start), 1 = fan linking pass, 2 = adjoint."""
+        return B.rtx_plan_region_stats(self._handle, region)
+
+    def timing(self, enable=True):
+        """Starts (resets) or stops per-kernel HIP-event timing of this plan."""
+        B.rtx_plan_timing(self._handle, enable)
+
+    def timings(self):
+        """{slot: (total ms, launches)} since timing(True); slots: pack, trace,
+        fan_seed, fan_link, adjoint."""
+        t, n = B.rtx_plan_timings(self._handle)
+        names = ("pack", "trace", "fan_seed", "fan_link", "adjoint")
+        return {k: (t[i], n[i]) for i, k in enumerate(names)}
 
     def set_launch(self, rays_per_block):
         """Rays (threads) per block of the persistent kernels: 64, 128 or 256."""

@@ -10,14 +10,16 @@ LIB_PATH = os.path.join(_HERE, "librtx.so")
 RTX_OK, RTX_E_ARG, RTX_E_HIP, RTX_E_NOMEM, RTX_E_UNSUPPORTED, RTX_E_CAPACITY = 0, -1, -2, -3, -4, -5
 RTX_F64, RTX_F32C = 0, 1
 RTX_HEUN, RTX_RK4 = 2, 4
-RTX_WARM_START, RTX_FIXED_ANGLE = 1, 2
+RTX_WARM_START, RTX_FIXED_ANGLE, RTX_FAN_START = 1, 2, 4
+RTX_SLOT_PACK, RTX_SLOT_TRACE, RTX_SLOT_FAN_SEED, RTX_SLOT_FAN_LINK, RTX_SLOT_ADJOINT, RTX_NUM_SLOTS = 0, 1, 2, 3, 4, 5
 RTX_W_LENGTH, RTX_W_DTDC = 0, 1
 RTX_RESID_REAL, RTX_RESID_RAYBORN_C64 = 0, 1
 RTX_RAY_LINKED, RTX_RAY_NOT_CONVERGED, RTX_RAY_NO_HIT, RTX_RAY_BAD_INPUT = 0, 1, 2, 3
 
 # every symbol include/rtx.h declares
 EXPORTS = ("rtx_plan_create", "rtx_plan_destroy", "rtx_plan_set_opts", "rtx_set_medium", "rtx_trace_rays",
-           "rtx_tof_forward", "rtx_tof_adjoint", "rtx_plan_stats", "rtx_plan_set_launch", "rtx_batch_create",
+           "rtx_tof_forward", "rtx_tof_adjoint", "rtx_plan_stats", "rtx_plan_region_stats", "rtx_plan_timing",
+           "rtx_plan_timings", "rtx_plan_set_launch", "rtx_batch_create",
            "rtx_batch_run", "rtx_batch_times", "rtx_batch_destroy", "rtx_last_error")
 
 
@@ -69,6 +71,9 @@ def load():
     L.rtx_tof_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(C.c_double), i32, i32, vp, vp]
     L.rtx_plan_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.rtx_plan_set_launch.argtypes = [vp, i32]
+    L.rtx_plan_region_stats.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i64)]
+    L.rtx_plan_timing.argtypes = [vp, i32]
+    L.rtx_plan_timings.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
     L.rtx_batch_create.argtypes = [C.POINTER(vp), C.POINTER(rtx_opts), i32, i32, i32, C.POINTER(rtx_instance)]
     L.rtx_batch_run.argtypes = [vp, vp]
     L.rtx_batch_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -153,3 +158,20 @@ def rtx_batch_times(batch, n_inst):
 
 def rtx_batch_destroy(batch):
     return check(load().rtx_batch_destroy(batch))
+
+
+def rtx_plan_region_stats(plan, region):
+    a, b = C.c_int64(), C.c_int64()
+    check(load().rtx_plan_region_stats(plan, int(region), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def rtx_plan_timing(plan, enable):
+    return check(load().rtx_plan_timing(plan, int(bool(enable))))
+
+
+def rtx_plan_timings(plan):
+    t = (C.c_double * RTX_NUM_SLOTS)()
+    n = (C.c_int32 * RTX_NUM_SLOTS)()
+    check(load().rtx_plan_timings(plan, t, n))
+    return list(t), list(n)

@@ -466,6 +466,16 @@ __device__ __forceinline__ double link_next_hit(Link &L, double g)
 }
 
 // ------------------------------------------------------------ trace kernel --
+// Fan start: the straight-ray rays of all receivers of an emitter sample one
+// function, the hit angle of a ray launched at theta; the nearest sign change of
+// the receiver's misfit over consecutive samples seeds its secant.
+struct FanSeed {
+    double th_far, g_far, th_near, g_near;  // bracket ends (larger |g| first)
+    int found;
+};
+
+constexpr uint32_t kStraight = 1u << 16;  // internal: fixed pass at straight angles
+
 struct TraceArgs {
     const int32_t *pairs;
     int64_t n_pairs;
@@ -476,6 +486,10 @@ struct TraceArgs {
     double tol;
     uint32_t flags;
     unsigned long long *stats;  // [gridDim.x][2]: steps, rays
+    double *gsig;               // fixed pass: signed misfit of each ray (or NULL)
+    const FanSeed *seed;        // fan start: per-pair seeds
+    const double *f_g, *f_T, *f_L;  // fan start: the pair's own straight ray
+    const int8_t *f_st;
 };
 
 __device__ __forceinline__ bool pair_of(const TraceArgs &A, const Geo &g, int64_t p, int &e, int &r)
@@ -583,7 +597,7 @@ __device__ __forceinline__ void mark_done(const BatchArgs &B, int k)
     if (atomicSub(B.remain + k, 1u) == 1u) B.t_done[k] = wall_clock64();
 }
 
-template <class R, bool COMP, int INTEG, bool BATCH>
+template <class R, bool COMP, int INTEG, bool BATCH, bool FAN = false>
 __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs A, BatchArgs B)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -623,13 +637,55 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
             if (pair_of(a, gg, q, e, r)) {
                 pe = elem_angle(gg, e);
                 dr = mod2pi(elem_angle(gg, r) - pe);
-                double th0 = (a.flags & (RTX_WARM_START | RTX_FIXED_ANGLE)) ? a.theta[q] : (dr - kPi) / 2.0;
+                const bool given = (a.flags & (RTX_WARM_START | RTX_FIXED_ANGLE)) && !(a.flags & kStraight);
+                double th0 = given ? a.theta[q] : (dr - kPi) / 2.0;
                 link_reset(L, th0);
-                start_ray<R, COMP>(ray, gg, e, th0);
+                double th = th0;
+                if (FAN) {
+                    // the pair's own straight ray was traced by the fixed pass
+                    L.n_marches = 1;
+                    int st0 = a.f_st[q];
+                    if (st0 == RTX_RAY_BAD_INPUT) {
+                        write_pair(a, q, th0, NAN, NAN, NAN, 1, RTX_RAY_BAD_INPUT);
+                        goto next;
+                    }
+                    if (st0 == RTX_RAY_LINKED) {
+                        double miss = fabs(a.f_g[q]) * gg.R;
+                        L.best_miss = miss;
+                        L.best_th = th0;
+                        L.best_T = a.f_T[q];
+                        L.best_L = a.f_L[q];
+                        if (miss <= a.tol) {
+                            write_pair(a, q, th0, a.f_T[q], a.f_L[q], miss, 1, RTX_RAY_LINKED);
+                            goto next;
+                        }
+                    }
+                    const FanSeed sd = a.seed[q];
+                    if (sd.found) {
+                        L.th = sd.th_far;
+                        link_next_hit(L, sd.g_far);
+                        L.th = sd.th_near;
+                        th = link_next_hit(L, sd.g_near);
+                    } else if (st0 == RTX_RAY_LINKED) {
+                        th = link_next_hit(L, a.f_g[q]);
+                    } else {
+                        th = 0.5 * th0;
+                    }
+                    L.th = th;
+                    if (L.n_marches >= a.max_marches) {  // only the straight ray was allowed
+                        if (L.best_miss < INFINITY)
+                            write_pair(a, q, L.best_th, L.best_T, L.best_L, L.best_miss, 1, RTX_RAY_NOT_CONVERGED);
+                        else
+                            write_pair(a, q, th0, NAN, NAN, NAN, 1, RTX_RAY_NO_HIT);
+                        goto next;
+                    }
+                }
+                start_ray<R, COMP>(ray, gg, e, th);
                 active = true;
                 return;
             }
             write_pair(a, q, a.theta[q], NAN, NAN, NAN, 0, RTX_RAY_BAD_INPUT);
+        next:
             if (BATCH) mark_done(B, k);
             p += stride;
         }
@@ -680,6 +736,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
         bool pair_done = false;
         if (a.flags & RTX_FIXED_ANGLE) {
             write_pair(a, q, L.th, T, Lm, fabs(g_mis) * gg.R, 1, st);
+            if (a.gsig) a.gsig[q] = g_mis;
             pair_done = true;
         } else if (st == RTX_RAY_BAD_INPUT) {
             write_pair(a, q, L.th0, NAN, NAN, NAN, L.n_marches, RTX_RAY_BAD_INPUT);
@@ -727,41 +784,59 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
 // ---------------------------------------------------------- adjoint kernel --
 
 
-// Pending hat weights of one cell visit.  Consecutive samples of a ray that
-// fall in the same cell add into registers; the four node atomics go out when
-// the ray leaves the cell (about one flush per 3-4 samples at ds = 0.25 px).
+// Pending hat weights of the current cell's four nodes.  Consecutive samples
+// of a ray in the same cell add into registers; when the ray moves to another
+// cell, the nodes it shares with the new cell keep their pending sums and only
+// the others are flushed with atomics (two per edge crossing, three per corner
+// crossing, instead of four per visit).
 template <class R>
 struct CellAcc {
     int64_t n0;  // node index of the cell's lower-left corner, -1 = empty
-    R a00, a10, a01, a11;
+    R a[4];      // nodes n0, n0 + 1, n0 + nx, n0 + nx + 1
 };
 
 template <class R>
 __device__ __forceinline__ void acc_flush(R *grad, int nx, CellAcc<R> &A)
 {
     if (A.n0 >= 0) {
-        unsafeAtomicAdd(grad + A.n0, A.a00);
-        unsafeAtomicAdd(grad + A.n0 + 1, A.a10);
-        unsafeAtomicAdd(grad + A.n0 + nx, A.a01);
-        unsafeAtomicAdd(grad + A.n0 + nx + 1, A.a11);
+        unsafeAtomicAdd(grad + A.n0, A.a[0]);
+        unsafeAtomicAdd(grad + A.n0 + 1, A.a[1]);
+        unsafeAtomicAdd(grad + A.n0 + nx, A.a[2]);
+        unsafeAtomicAdd(grad + A.n0 + nx + 1, A.a[3]);
     }
     A.n0 = -1;
-    A.a00 = A.a10 = A.a01 = A.a11 = (R)0;
+    A.a[0] = A.a[1] = A.a[2] = A.a[3] = (R)0;
+}
+
+template <class R>
+__device__ __forceinline__ void acc_move(R *grad, int nx, CellAcc<R> &A, int64_t n0)
+{
+    R b[4] = {(R)0, (R)0, (R)0, (R)0};
+    if (A.n0 >= 0) {
+        const int64_t old[4] = {A.n0, A.n0 + 1, A.n0 + nx, A.n0 + nx + 1};
+        for (int k = 0; k < 4; k++) {
+            int64_t d = old[k] - n0;
+            int slot = d == 0 ? 0 : d == 1 ? 1 : d == nx ? 2 : d == nx + 1 ? 3 : -1;
+            if (slot >= 0)
+                b[slot] += A.a[k];
+            else
+                unsafeAtomicAdd(grad + old[k], A.a[k]);
+        }
+    }
+    A.n0 = n0;
+    for (int k = 0; k < 4; k++) A.a[k] = b[k];
 }
 
 template <class R>
 __device__ __forceinline__ void acc_add(R *grad, int nx, CellAcc<R> &A, const Sample<R> &s, R a)
 {
     int64_t n0 = (int64_t)s.iy * nx + s.ix;
-    if (n0 != A.n0) {
-        acc_flush(grad, nx, A);
-        A.n0 = n0;
-    }
+    if (n0 != A.n0) acc_move(grad, nx, A, n0);
     R omt = (R)1 - s.t, oms = (R)1 - s.s;
-    A.a00 = fma(a * omt, oms, A.a00);
-    A.a10 = fma(a * s.t, oms, A.a10);
-    A.a01 = fma(a * omt, s.s, A.a01);
-    A.a11 = fma(a * s.t, s.s, A.a11);
+    A.a[0] = fma(a * omt, oms, A.a[0]);
+    A.a[1] = fma(a * s.t, oms, A.a[1]);
+    A.a[2] = fma(a * omt, s.s, A.a[2]);
+    A.a[3] = fma(a * s.t, s.s, A.a[3]);
 }
 
 template <class R, bool COMP, int INTEG, bool BATCH>
@@ -781,7 +856,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
     Ray<R> ray;
     CellAcc<R> acc;
     acc.n0 = -1;
-    acc.a00 = acc.a10 = acc.a01 = acc.a11 = (R)0;
+    acc.a[0] = acc.a[1] = acc.a[2] = acc.a[3] = (R)0;
     R scale = 0;  // rho h
     bool active = false;
 
@@ -869,6 +944,58 @@ __global__ void k_batch_reset(const int64_t *__restrict__ off, int n_inst, unsig
         remain_adj[k] = n;
     }
     if (k == 0) *t0 = wall_clock64();
+}
+
+// One block per emitter e (all ordered pairs in canonical order): samples
+// G_j = H_j - D_r of the straight rays at offsets j = 1..n-1 with
+// H_j = g_j + D_j; each receiver takes the sign change over consecutive samples
+// nearest to its own offset, searched outward (own, own+1, own-1-1, ...).
+__global__ void __launch_bounds__(kBlock) k_fan_seed(Geo g, const double *__restrict__ f_g,
+                                                     const int8_t *__restrict__ f_st, FanSeed *__restrict__ seed)
+{
+    extern __shared__ double H[];  // [n-1] hit angle of the ray at offset j (NaN: no hit)
+    const int n = g.n_elem, e = blockIdx.x;
+    const double pe = elem_angle(g, e);
+    for (int j = 1 + threadIdx.x; j < n; j += blockDim.x) {
+        int k = (e + j) % n;
+        int64_t i = (int64_t)e * (n - 1) + (k < e ? k : k - 1);
+        double Dj = mod2pi(elem_angle(g, k) - pe);
+        H[j - 1] = f_st[i] == RTX_RAY_LINKED ? f_g[i] + Dj : NAN;
+    }
+    __syncthreads();
+    for (int jr = 1 + threadIdx.x; jr < n; jr += blockDim.x) {
+        int r = (e + jr) % n;
+        int64_t i = (int64_t)e * (n - 1) + (r < e ? r : r - 1);
+        double Dr = mod2pi(elem_angle(g, r) - pe);
+        int found = -1;
+        for (int d = 0; d < n && found < 0; d++) {
+            int cand[2] = {jr - 1 + d, jr - 1 - d - 1};
+            for (int c = 0; c < 2; c++) {
+                int a = cand[c];
+                if (a < 0 || a + 1 > n - 2) continue;
+                double ga = H[a] - Dr, gb = H[a + 1] - Dr;
+                if (ga == ga && gb == gb && ga * gb <= 0.0) {
+                    found = a;
+                    break;
+                }
+            }
+        }
+        FanSeed sd;
+        sd.found = found >= 0;
+        sd.th_far = sd.g_far = sd.th_near = sd.g_near = 0.0;
+        if (found >= 0) {
+            double ga = H[found] - Dr, gb = H[found + 1] - Dr;
+            int nr = fabs(ga) <= fabs(gb) ? found : found + 1;
+            int fr = nr == found ? found + 1 : found;
+            double gn = nr == found ? ga : gb, gf = nr == found ? gb : ga;
+            int kn = (e + nr + 1) % n, kf = (e + fr + 1) % n;
+            sd.th_near = (mod2pi(elem_angle(g, kn) - pe) - kPi) / 2.0;
+            sd.th_far = (mod2pi(elem_angle(g, kf) - pe) - kPi) / 2.0;
+            sd.g_near = gn;
+            sd.g_far = gf;
+        }
+        seed[i] = sd;
+    }
 }
 
 // ------------------------------------------------------------ path weights --
@@ -1132,13 +1259,21 @@ struct rtx_plan_s {
     int64_t max_pairs;
     void *tab = nullptr;  // packed medium
     bool have_medium = false;
-    unsigned long long *stats = nullptr;  // [kMaxBlocks][2] trace, then adjoint
-    int stat_blocks_trace = 0, stat_blocks_adj = 0;
+    unsigned long long *stats = nullptr;  // [3][kMaxBlocks][2]: trace, fan link pass, adjoint
+    int stat_blocks[3] = {0, 0, 0};
     double *rho = nullptr;     // [max_pairs] ray-Born reduction
     double *omega = nullptr;   // [n_freq_cap]
     int n_freq_cap = 0;
     int n_cu = 0;
     int block = kBlock;  // threads (rays) per block of the persistent kernels
+    // fan-start workspace (allocated on first use): own straight ray of each pair
+    double *f_g = nullptr, *f_T = nullptr, *f_L = nullptr;
+    int8_t *f_st = nullptr;
+    void *f_seed = nullptr;
+    // optional per-kernel timing with HIP events on the launch stream
+    bool timing = false;
+    std::vector<hipEvent_t> ev[RTX_NUM_SLOTS];
+    int ev_used[RTX_NUM_SLOTS] = {};
 };
 
 struct rtx_batch_s {
@@ -1209,6 +1344,21 @@ int max_steps_of(const rtx_plan_s *P)
     return (int)ceil(8.0 * (P->ring.radius / P->grid.h) / P->opts.ds_px);
 }
 
+// Event pair bracketing one launch when the plan's timing is on.
+int time_mark(rtx_plan_s *P, int slot, int end, hipStream_t s)
+{
+    if (!P->timing) return RTX_OK;
+    int k = P->ev_used[slot] * 2 + end;
+    while ((int)P->ev[slot].size() <= k) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        P->ev[slot].push_back(e);
+    }
+    HIP_TRY(hipEventRecord(P->ev[slot][k], s));
+    if (end) P->ev_used[slot]++;
+    return RTX_OK;
+}
+
 int pack(rtx_plan_s *P, const double *c, hipStream_t s)
 {
     if (!c) {
@@ -1217,6 +1367,7 @@ int pack(rtx_plan_s *P, const double *c, hipStream_t s)
     }
     int64_t cells = (int64_t)(P->grid.nx - 1) * (P->grid.ny - 1);
     int blocks = (int)((cells + kBlock - 1) / kBlock);
+    if (int rc = time_mark(P, RTX_SLOT_PACK, 0, s)) return rc;
     if (P->opts.prec == RTX_F32C)
         hipLaunchKernelGGL(k_pack<float>, dim3(blocks), dim3(kBlock), 0, s, c, P->grid.nx, P->grid.ny,
                            (float *)P->tab);
@@ -1225,7 +1376,7 @@ int pack(rtx_plan_s *P, const double *c, hipStream_t s)
                            (double *)P->tab);
     HIP_TRY(hipGetLastError());
     P->have_medium = true;
-    return RTX_OK;
+    return time_mark(P, RTX_SLOT_PACK, 1, s);
 }
 
 // Persistent launch: no more blocks than can be resident at once (lanes take
@@ -1247,18 +1398,61 @@ int grid_blocks(const rtx_plan_s *P, K kernel, int64_t n)
     return grid_blocks_for(P->n_cu, P->block, kernel, n);
 }
 
-template <class R, bool COMP>
-int launch_trace(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
+template <class R, bool COMP, bool FAN = false>
+int launch_trace(rtx_plan_s *P, const TraceArgs &A, hipStream_t s, int region = 0, int slot = RTX_SLOT_TRACE)
 {
     Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
     Geo g = make_geo(P);
-    auto kern = P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false> : k_trace<R, COMP, 2, false>;
+    auto kern = P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false, FAN> : k_trace<R, COMP, 2, false, FAN>;
     int blocks = grid_blocks(P, kern, A.n_pairs);
-    P->stat_blocks_trace = blocks;
+    P->stat_blocks[region] = blocks;
     BatchArgs B{};
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(P->block), 0, s, M, g, A, B);
+    TraceArgs a = A;
+    a.stats = P->stats + (size_t)region * 2 * kMaxBlocks;
+    if (int rc = time_mark(P, slot, 0, s)) return rc;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(P->block), 0, s, M, g, a, B);
     HIP_TRY(hipGetLastError());
-    return RTX_OK;
+    return time_mark(P, slot, 1, s);
+}
+
+// Fan start: fixed pass at straight angles, seeds, linking pass.
+template <class R, bool COMP>
+int launch_fan(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
+{
+    const int64_t n = A.n_pairs;
+    if (!P->f_g) {
+        if (hipMalloc((void **)&P->f_g, sizeof(double) * P->max_pairs) != hipSuccess ||
+            hipMalloc((void **)&P->f_T, sizeof(double) * P->max_pairs) != hipSuccess ||
+            hipMalloc((void **)&P->f_L, sizeof(double) * P->max_pairs) != hipSuccess ||
+            hipMalloc((void **)&P->f_st, sizeof(int8_t) * P->max_pairs) != hipSuccess ||
+            hipMalloc(&P->f_seed, sizeof(FanSeed) * P->max_pairs) != hipSuccess)
+            return fail(RTX_E_NOMEM, "fan-start workspace");
+    }
+    TraceArgs A1 = A;
+    A1.flags = RTX_FIXED_ANGLE | kStraight;
+    A1.tof = P->f_T;
+    A1.len = P->f_L;
+    A1.miss = nullptr;
+    A1.n_marches = nullptr;
+    A1.status = P->f_st;
+    A1.gsig = P->f_g;
+    if (int rc = launch_trace<R, COMP>(P, A1, s, 0, RTX_SLOT_TRACE)) return rc;
+    Geo g = make_geo(P);
+    if (int rc = time_mark(P, RTX_SLOT_FAN_SEED, 0, s)) return rc;
+    hipLaunchKernelGGL(k_fan_seed, dim3(P->ring.n_elem), dim3(kBlock), sizeof(double) * (P->ring.n_elem - 1), s, g,
+                       P->f_g, P->f_st, (FanSeed *)P->f_seed);
+    HIP_TRY(hipGetLastError());
+    if (int rc = time_mark(P, RTX_SLOT_FAN_SEED, 1, s)) return rc;
+    TraceArgs A3 = A;
+    A3.flags = RTX_FAN_START;
+    A3.gsig = nullptr;
+    A3.seed = (const FanSeed *)P->f_seed;
+    A3.f_g = P->f_g;
+    A3.f_T = P->f_T;
+    A3.f_L = P->f_L;
+    A3.f_st = P->f_st;
+    (void)n;
+    return launch_trace<R, COMP, true>(P, A3, s, 1, RTX_SLOT_FAN_LINK);
 }
 
 template <class R, bool COMP>
@@ -1268,11 +1462,12 @@ int launch_adjoint(rtx_plan_s *P, const AdjArgs &A, R *grad, hipStream_t s)
     Geo g = make_geo(P);
     auto kern = P->opts.integ == RTX_RK4 ? k_adjoint<R, COMP, 4, false> : k_adjoint<R, COMP, 2, false>;
     int blocks = grid_blocks(P, kern, A.n_pairs);
-    P->stat_blocks_adj = blocks;
+    P->stat_blocks[2] = blocks;
     BatchArgs B{};
+    if (int rc = time_mark(P, RTX_SLOT_ADJOINT, 0, s)) return rc;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(P->block), 0, s, M, g, A, grad, B);
     HIP_TRY(hipGetLastError());
-    return RTX_OK;
+    return time_mark(P, RTX_SLOT_ADJOINT, 1, s);
 }
 
 constexpr int kMergeCap = 8192;  // entries per row the LDS merge can sort
@@ -1506,7 +1701,7 @@ int rtx_plan_create(rtx_plan *out, const rtx_grid *grid, const rtx_ring *ring, c
     }
     P->n_cu = prop.multiProcessorCount;
     if (hipMalloc(&P->tab, tab_bytes) != hipSuccess ||
-        hipMalloc((void **)&P->stats, sizeof(unsigned long long) * 2 * kMaxBlocks * 2) != hipSuccess ||
+        hipMalloc((void **)&P->stats, sizeof(unsigned long long) * 3 * 2 * kMaxBlocks) != hipSuccess ||
         hipMalloc((void **)&P->rho, sizeof(double) * max_pairs) != hipSuccess) {
         rtx_plan_destroy(P);
         return fail(RTX_E_NOMEM, "device allocation of the plan workspace failed");
@@ -1521,6 +1716,10 @@ int rtx_plan_destroy(rtx_plan P)
     (void)hipDeviceSynchronize();
     if (P->tab) (void)hipFree(P->tab);
     if (P->stats) (void)hipFree(P->stats);
+    for (void *q : {(void *)P->f_g, (void *)P->f_T, (void *)P->f_L, (void *)P->f_st, P->f_seed})
+        if (q) (void)hipFree(q);
+    for (int k = 0; k < RTX_NUM_SLOTS; k++)
+        for (hipEvent_t e : P->ev[k]) (void)hipEventDestroy(e);
     if (P->rho) (void)hipFree(P->rho);
     if (P->omega) (void)hipFree(P->omega);
     delete P;
@@ -1582,12 +1781,20 @@ int rtx_trace_rays(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_
     A.tol = P->opts.tol_px;
     A.flags = P->opts.flags;
     A.stats = P->stats;
+    A.gsig = nullptr;
+    A.seed = nullptr;
+    A.f_g = A.f_T = A.f_L = nullptr;
+    A.f_st = nullptr;
+    P->stat_blocks[1] = 0;
+    const bool fan = (A.flags & RTX_FAN_START) != 0;
+    if (fan && (pairs || (A.flags & (RTX_FIXED_ANGLE | RTX_WARM_START))))
+        return fail(RTX_E_ARG, "RTX_FAN_START needs all ordered pairs (pairs == NULL) and no warm/fixed start");
     if (P->opts.prec == RTX_F32C) {
-        rc = launch_trace<float, true>(P, A, s);
+        rc = fan ? launch_fan<float, true>(P, A, s) : launch_trace<float, true>(P, A, s);
         if (rc || !w_rowptr) return rc;
         return emit_weights<float, true>(P, A, w_rowptr, w_col, (float *)w_val, nnz_cap, s);
     }
-    rc = launch_trace<double, false>(P, A, s);
+    rc = fan ? launch_fan<double, false>(P, A, s) : launch_trace<double, false>(P, A, s);
     if (rc || !w_rowptr) return rc;
     return emit_weights<double, false>(P, A, w_rowptr, w_col, (double *)w_val, nnz_cap, s);
 }
@@ -1650,7 +1857,7 @@ int rtx_tof_adjoint(rtx_plan P, const double *c, const int32_t *pairs, int64_t n
     A.rho = rho;
     A.weight = weight;
     A.max_steps = max_steps_of(P);
-    A.stats = P->stats + 2 * kMaxBlocks;
+    A.stats = P->stats + 2 * 2 * kMaxBlocks;
     if (P->opts.prec == RTX_F32C) return launch_adjoint<float, true>(P, A, (float *)grad, s);
     return launch_adjoint<double, false>(P, A, (double *)grad, s);
 }
@@ -1660,17 +1867,64 @@ int rtx_plan_stats(rtx_plan P, int64_t *trace_steps, int64_t *trace_rays, int64_
     g_last_error.clear();
     if (!P) return fail(RTX_E_ARG, "null plan");
     HIP_TRY(hipDeviceSynchronize());
-    std::vector<unsigned long long> h(4 * kMaxBlocks);
-    HIP_TRY(hipMemcpy(h.data(), P->stats, sizeof(unsigned long long) * 4 * kMaxBlocks, hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> h(6 * kMaxBlocks);
+    HIP_TRY(hipMemcpy(h.data(), P->stats, sizeof(unsigned long long) * 6 * kMaxBlocks, hipMemcpyDeviceToHost));
     unsigned long long ts = 0, tr = 0, as = 0;
-    for (int b = 0; b < P->stat_blocks_trace; b++) {
-        ts += h[2 * b];
-        tr += h[2 * b + 1];
-    }
-    for (int b = 0; b < P->stat_blocks_adj; b++) as += h[2 * kMaxBlocks + 2 * b];
+    for (int region = 0; region < 2; region++)
+        for (int b = 0; b < P->stat_blocks[region]; b++) {
+            ts += h[(size_t)region * 2 * kMaxBlocks + 2 * b];
+            tr += h[(size_t)region * 2 * kMaxBlocks + 2 * b + 1];
+        }
+    for (int b = 0; b < P->stat_blocks[2]; b++) as += h[4 * (size_t)kMaxBlocks + 2 * b];
     if (trace_steps) *trace_steps = (int64_t)ts;
     if (trace_rays) *trace_rays = (int64_t)tr;
     if (adjoint_steps) *adjoint_steps = (int64_t)as;
+    return RTX_OK;
+}
+
+int rtx_plan_region_stats(rtx_plan P, int32_t region, int64_t *steps, int64_t *rays)
+{
+    g_last_error.clear();
+    if (!P || region < 0 || region > 2) return fail(RTX_E_ARG, "null plan or region outside 0..2");
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<unsigned long long> h(2 * kMaxBlocks);
+    HIP_TRY(hipMemcpy(h.data(), P->stats + (size_t)region * 2 * kMaxBlocks, sizeof(unsigned long long) * 2 * kMaxBlocks,
+                      hipMemcpyDeviceToHost));
+    unsigned long long a = 0, b = 0;
+    for (int k = 0; k < P->stat_blocks[region]; k++) {
+        a += h[2 * k];
+        b += h[2 * k + 1];
+    }
+    if (steps) *steps = (int64_t)a;
+    if (rays) *rays = (int64_t)b;
+    return RTX_OK;
+}
+
+int rtx_plan_timing(rtx_plan P, int32_t enable)
+{
+    g_last_error.clear();
+    if (!P) return fail(RTX_E_ARG, "null plan");
+    HIP_TRY(hipDeviceSynchronize());
+    P->timing = enable != 0;
+    for (int k = 0; k < RTX_NUM_SLOTS; k++) P->ev_used[k] = 0;
+    return RTX_OK;
+}
+
+int rtx_plan_timings(rtx_plan P, double *total_ms, int32_t *count)
+{
+    g_last_error.clear();
+    if (!P || !total_ms || !count) return fail(RTX_E_ARG, "null argument");
+    HIP_TRY(hipDeviceSynchronize());
+    for (int k = 0; k < RTX_NUM_SLOTS; k++) {
+        double t = 0;
+        for (int i = 0; i < P->ev_used[k]; i++) {
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, P->ev[k][2 * i], P->ev[k][2 * i + 1]));
+            t += ms;
+        }
+        total_ms[k] = t;
+        count[k] = P->ev_used[k];
+    }
     return RTX_OK;
 }
 

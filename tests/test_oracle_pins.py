@@ -386,3 +386,55 @@ def test_rayborn_rho_is_derivative_of_phase_data(orc):
         dt = 1e-12
         fd = (F(T[i] + dt, i) - F(T[i] - dt, i)) / (2 * dt)
         assert abs(fd - rho[i]) < 1e-5 * np.abs(rho).max()
+
+
+# -------------------------------------------------------------- fan start --
+def test_fan_start_homogeneous_links_on_the_straight_rays(orc):
+    n, h = 64, 1e-3
+    ring = (16, 0.025, 0.3)
+    pairs = synth.all_pairs(16)
+    o = orc.trace(orc.grid_medium(synth.homogeneous(n, n), h), ring, pairs, fan=True)
+    assert np.all(o["status"] == orc.LINKED) and np.all(o["n_marches"] == 1)
+
+
+@pytest.mark.parametrize("G", [(400.0, 0.0), (250.0, 300.0)])
+def test_fan_start_linear_gradient_closed_form(orc, G):
+    nx, ny, h, c0 = 96, 80, 0.5e-3, 1500.0
+    c = synth.linear_gradient(nx, ny, h, c0, *G)
+    ring = (12, 0.018, 0.2)
+    pairs = synth.all_pairs(12)
+    o = orc.trace(orc.grid_medium(c, h), ring, pairs, tol_px=1e-10, fan=True)
+    pts, _ = cf.ring_points(*ring)
+    assert np.all(o["status"] == orc.LINKED)
+    for i, (e, r) in enumerate(pairs):
+        assert abs(o["tof"][i] / cf.linear_tof(pts[e], pts[r], c0, G) - 1) < 1e-9
+
+
+def test_fan_start_same_roots_fewer_rays(orc):
+    """Same roots as the straight start (within the tolerance band), in at most
+    as many rays per pair in total and fewer in the worst case."""
+    n, h = 128, 0.5e-3
+    c = synth.gaussian_inclusions(n, n, h, seed=7, r_max=0.022)
+    ring = (48, 0.030, 0.05)
+    pairs = synth.all_pairs(48)
+    med = orc.grid_medium(c, h)
+    a = orc.trace(med, ring, pairs)
+    b = orc.trace(med, ring, pairs, fan=True)
+    assert np.all(a["status"] == orc.LINKED) and np.all(b["status"] == orc.LINKED)
+    R_px = 0.030 / h
+    assert np.abs(a["theta"] - b["theta"]).max() < 4e-3 / R_px / 0.05
+    assert b["n_marches"].sum() <= a["n_marches"].sum()
+    assert b["n_marches"].max() < a["n_marches"].max()
+    with pytest.raises(ValueError):
+        orc.trace(med, ring, pairs[::2], fan=True)  # needs every ordered pair
+
+
+def test_fan_start_fisheye_reversed_orientation(orc):
+    cfg, c = synth.make_config("c1_fisheye_128")
+    ring = (32, cfg["radius"], 0.0)
+    pairs = synth.all_pairs(32)
+    a = orc.trace(orc.grid_medium(c, cfg["h"]), ring, pairs)
+    b = orc.trace(orc.grid_medium(c, cfg["h"]), ring, pairs, fan=True)
+    assert np.all(b["status"] == orc.LINKED)
+    assert np.abs(a["tof"] / b["tof"] - 1).max() < 1e-5
+    assert b["n_marches"].mean() < a["n_marches"].mean()
