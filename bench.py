@@ -158,6 +158,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--fan-only", action="store_true", help="skip the straight-start comparison runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device copy (the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profile)")
@@ -182,7 +183,7 @@ def main():
 
     runs = {}
     for prec in ("f32c",) + (() if args.no_f64 else ("f64",)):
-        for fan in (True, False):
+        for fan in (True,) if args.fan_only else (True, False):
             r, _ = run_gpu(prec, c, cfg, args.steps, args.warmup, resid, fan=fan)
             runs[(prec, fan)] = r
             print(f"# {prec} {r['linking_start']}: {r['ms_per_step']:.3f} ms/step, forward {r['forward_ms']:.3f} ms "

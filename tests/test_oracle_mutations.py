@@ -28,6 +28,10 @@ MUTATIONS = {
                      "d = c[iy * nx + 1] - c[iy * nx + 0];"),
     "dtdc_kappa": ("kappa = -1.0 / (cc * cc);", "kappa = -1.0 / cc;"),
     "rayborn_sign": ("acc += w * (im * cos(ph) - re * sin(ph));", "acc += w * (im * cos(ph) + re * sin(ph));"),
+    "fan_sample_angle_off_by_one": ("TH[j - 1] = straight_angle(ring, e, k);",
+                                    "TH[j - 1] = straight_angle(ring, e, (k + 1) % n);"),
+    "fan_target_wrong_receiver": ("G[j - 1] = row[j - 1].st == ST_LINKED ? (row[j - 1].g + Dj) - Dr : NAN;",
+                                  "G[j - 1] = row[j - 1].st == ST_LINKED ? row[j - 1].g - Dr : NAN;"),
 }
 
 PINS = [
@@ -47,6 +51,8 @@ PINS = [
     lambda o: P.test_adjoint_is_transpose_of_weights(o),
     lambda o: P.test_dtdc_adjoint_matches_finite_differences(o),
     lambda o: P.test_rayborn_rho_is_derivative_of_phase_data(o),
+    lambda o: P.test_fan_start_same_roots_fewer_rays(o),
+    lambda o: P.test_fan_start_fisheye_reversed_orientation(o),
 ]
 
 
