@@ -6,7 +6,8 @@ built with gcc into ``liboracle_rt.so`` next to it; this module only marshals
 numpy arrays.  It shares no code with the HIP path.
 
 Media are described by a dict:
-  {"kind": "grid", "c": float64[ny, nx], "h": h}
+  {"kind": "grid", "c": float64[ny, nx], "h": h}          (bilinear)
+  {"kind": "grid_bspline", "c": float64[ny, nx], "h": h}  (cubic B-spline)
   {"kind": "fisheye", "nx": nx, "ny": ny, "h": h, "c0": c0, "R": R}   (analytic)
   {"kind": "linear", "nx": nx, "ny": ny, "h": h, "c0": c0, "ax": ax, "ay": ay}
 """
@@ -106,10 +107,10 @@ def _b(a):
 def _medium_args(medium):
     kind = medium["kind"]
     h = float(medium["h"])
-    if kind == "grid":
+    if kind in ("grid", "grid_bspline"):
         c = np.ascontiguousarray(medium["c"], dtype=np.float64)
         ny, nx = c.shape
-        return [0, nx, ny, h, _d(c), None], (c,)
+        return [0 if kind == "grid" else 3, nx, ny, h, _d(c), None], (c,)
     par = np.zeros(4)
     if kind == "fisheye":
         par[:2] = (medium["c0"], medium["R"])
@@ -122,8 +123,9 @@ def _medium_args(medium):
     return [code, int(medium.get("nx", 8)), int(medium.get("ny", 8)), h, None, _d(par)], (par,)
 
 
-def grid_medium(c, h):
-    return {"kind": "grid", "c": np.asarray(c, dtype=np.float64), "h": float(h)}
+def grid_medium(c, h, interp="bilinear"):
+    kind = {"bilinear": "grid", "bspline": "grid_bspline"}[interp]
+    return {"kind": kind, "c": np.asarray(c, dtype=np.float64), "h": float(h)}
 
 
 def gradient(c):

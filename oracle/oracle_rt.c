@@ -44,6 +44,7 @@
 #define OR_GRID 0
 #define OR_FISHEYE 1 /* analytic c = c0 (1 + |x|^2 / R^2), params {c0, R} */
 #define OR_LINEAR 2  /* analytic c = c0 + ax x + ay y,   params {c0, ax, ay} */
+#define OR_BSPLINE 3 /* grid, cubic B-spline interpolation of c (gradient analytic) */
 
 #define ST_LINKED 0
 #define ST_NOT_CONVERGED 1
@@ -62,6 +63,7 @@ typedef struct {
     double h;
     const double *c; /* [ny][nx] */
     double *gx, *gy; /* per-pixel gradient of c on nodes */
+    double *bs;      /* cubic B-spline coefficients of c (OR_BSPLINE) */
     double p[4];
 } Medium;
 
@@ -150,9 +152,85 @@ static void hat4(double t, double s, double w[4])
     w[3] = t * s;
 }
 
+/* ----------------------------------------------------------- cubic B-spline -- */
+/* Sec. 3.3: cubic B-spline interpolation, control points at the grid nodes, C2
+   field, first derivatives analytic, 4-node stencil per axis.  Reading: the
+   interpolating spline (its coefficients solve sum_k b(k - j) coef_k = c_j with
+   the centred cubic B-spline b, so the spline passes through the node values),
+   mirror-symmetric extension at the grid edges.  The coefficients come from the
+   standard two-pass recursive filter with pole z = sqrt(3) - 2 (causal then
+   anti-causal, gain 6), applied along x then along y. */
+static void bspline_filter_line(double *v, int n, int stride)
+{
+    const double z = sqrt(3.0) - 2.0;
+    /* causal initialisation: sum over the mirror-extended signal of v[k] z^k,
+       in closed form for the period-2(n-1) extension */
+    double zn = z, iz = 1.0 / z, z2n = pow(z, (double)(n - 1));
+    double sum = v[0] + z2n * v[(n - 1) * stride];
+    z2n *= z2n * iz;
+    for (int k = 1; k <= n - 2; k++) {
+        sum += (zn + z2n) * v[k * stride];
+        zn *= z;
+        z2n *= iz;
+    }
+    v[0] = sum / (1.0 - zn * zn);
+    for (int k = 1; k < n; k++) v[k * stride] += z * v[(k - 1) * stride];
+    /* anti-causal initialisation for the mirror boundary */
+    v[(n - 1) * stride] = (z / (z * z - 1.0)) * (v[(n - 1) * stride] + z * v[(n - 2) * stride]);
+    for (int k = n - 2; k >= 0; k--) v[k * stride] = z * (v[(k + 1) * stride] - v[k * stride]);
+    for (int k = 0; k < n; k++) v[k * stride] *= 6.0;
+}
+
+/* centred cubic B-spline weights of the nodes at offsets -1, 0, 1, 2 from the
+   cell's lower node, local coordinate t in [0, 1], and their derivatives */
+static void bspline_w(double t, double w[4], double dw[4])
+{
+    double u = 1.0 - t;
+    w[0] = u * u * u / 6.0;
+    w[1] = (3.0 * t * t * t - 6.0 * t * t + 4.0) / 6.0;
+    w[2] = (-3.0 * t * t * t + 3.0 * t * t + 3.0 * t + 1.0) / 6.0;
+    w[3] = t * t * t / 6.0;
+    dw[0] = -u * u / 2.0;
+    dw[1] = (3.0 * t * t - 4.0 * t) / 2.0;
+    dw[2] = (-3.0 * t * t + 2.0 * t + 1.0) / 2.0;
+    dw[3] = t * t / 2.0;
+}
+
+static int mirror(int i, int n)
+{
+    if (i < 0) return -i;
+    if (i > n - 1) return 2 * (n - 1) - i;
+    return i;
+}
+
 /* c (m/s) and its per-pixel gradient at pixel position (px, py). */
 static void medium_eval(const Medium *m, double px, double py, double *c, double *gx, double *gy)
 {
+    if (m->kind == OR_BSPLINE) {
+        int ix, iy;
+        double t, s, wx[4], dwx[4], wy[4], dwy[4];
+        if (!locate(m, px, py, &ix, &iy, &t, &s)) {
+            *c = *gx = *gy = NAN;
+            return;
+        }
+        bspline_w(t, wx, dwx);
+        bspline_w(s, wy, dwy);
+        double v = 0, vx = 0, vy = 0;
+        for (int b = 0; b < 4; b++) {
+            int jy = mirror(iy - 1 + b, m->ny);
+            for (int a = 0; a < 4; a++) {
+                int jx = mirror(ix - 1 + a, m->nx);
+                double cf = m->bs[jy * m->nx + jx];
+                v += cf * wx[a] * wy[b];
+                vx += cf * dwx[a] * wy[b];
+                vy += cf * wx[a] * dwy[b];
+            }
+        }
+        *c = v;
+        *gx = vx;
+        *gy = vy;
+        return;
+    }
     if (m->kind == OR_FISHEYE) {
         double x = px * m->h, y = py * m->h, c0 = m->p[0], R = m->p[1];
         *c = c0 * (1.0 + (x * x + y * y) / (R * R));
@@ -619,6 +697,13 @@ static int setup(int kind, int nx, int ny, double h, const double *c, const doub
         m->gy = (double *)malloc(sizeof(double) * nx * ny);
         or_gradient(nx, ny, c, m->gx, m->gy);
     }
+    if (kind == OR_BSPLINE) {
+        if (nx < 4 || ny < 4 || !c) return -1;
+        m->bs = (double *)malloc(sizeof(double) * nx * ny);
+        memcpy(m->bs, c, sizeof(double) * nx * ny);
+        for (int iy = 0; iy < ny; iy++) bspline_filter_line(m->bs + (size_t)iy * nx, nx, 1);
+        for (int ix = 0; ix < nx; ix++) bspline_filter_line(m->bs + ix, ny, nx);
+    }
     ring->n_elem = n_elem;
     ring->radius_px = radius / h;
     ring->phi0 = phi0;
@@ -635,6 +720,7 @@ static void teardown(Medium *m)
 {
     free(m->gx);
     free(m->gy);
+    free(m->bs);
 }
 
 /* Per pair (e, r): theta [in: warm start / fixed angle | out: linked angle],

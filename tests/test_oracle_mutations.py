@@ -30,6 +30,14 @@ MUTATIONS = {
     "rayborn_sign": ("acc += w * (im * cos(ph) - re * sin(ph));", "acc += w * (im * cos(ph) + re * sin(ph));"),
     "fan_sample_angle_off_by_one": ("TH[j - 1] = straight_angle(ring, e, k);",
                                     "TH[j - 1] = straight_angle(ring, e, (k + 1) % n);"),
+    "bspline_gain_dropped": ("for (int k = 0; k < n; k++) v[k * stride] *= 6.0;",
+                             "for (int k = 0; k < n; k++) v[k * stride] *= 1.0;"),
+    "bspline_anticausal_init": ("v[(n - 1) * stride] = (z / (z * z - 1.0)) * (v[(n - 1) * stride] + z * v[(n - 2) * stride]);",
+                                "v[(n - 1) * stride] = (z / (z * z - 1.0)) * v[(n - 1) * stride];"),
+    "bspline_weight_term_sign": ("w[2] = (-3.0 * t * t * t + 3.0 * t * t + 3.0 * t + 1.0) / 6.0;",
+                                 "w[2] = (-3.0 * t * t * t - 3.0 * t * t + 3.0 * t + 1.0) / 6.0;"),
+    "bspline_derivative_sign": ("dw[0] = -u * u / 2.0;", "dw[0] = u * u / 2.0;"),
+    "bspline_half_sample_mirror": ("if (i < 0) return -i;", "if (i < 0) return -i - 1;"),
     "fan_target_wrong_receiver": ("G[j - 1] = row[j - 1].st == ST_LINKED ? (row[j - 1].g + Dj) - Dr : NAN;",
                                   "G[j - 1] = row[j - 1].st == ST_LINKED ? row[j - 1].g - Dr : NAN;"),
 }
@@ -38,6 +46,8 @@ PINS = [
     lambda o: P.test_gradient_exact_on_quadratics(o),
     lambda o: P.test_gradient_is_not_transposed(o),
     lambda o: P.test_bilinear_exact_and_gradient_of_quadratic(o),
+    lambda o: P.test_bspline_matches_library_mirror_spline(o),
+    lambda o: P.test_bspline_reproduces_cubics_in_the_interior(o),
     lambda o: P.test_homogeneous_straight_rays(o),
     lambda o: P.test_homogeneous_weights_are_hat_line_integrals(o),
     lambda o: P.test_linear_gradient_closed_form(o, (250.0, 300.0), "rk4"),
