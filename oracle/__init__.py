@@ -61,6 +61,7 @@ def _load(path):
     L.or_march_points.argtypes = med + [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int,
                                         C.c_int, C.c_int, C.c_double, _dp, C.c_int, _dp, _dp]
     L.or_march_free.argtypes = med + [C.c_int, C.c_double, _dp, _dp, C.c_int, _dp]
+    L.or_fan_cubic.argtypes = [_dp, _dp, C.c_int, C.c_int, _dp]
     L.or_interp.argtypes = med + [C.c_int, _dp, _dp, _dp, _dp]
     L.or_weights_row.argtypes = [C.c_int, C.c_int, C.c_double, _dp, C.c_int, C.c_double, C.c_double,
                                  C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double, _ip, _dp,
@@ -251,6 +252,16 @@ def adjoint(c, h, ring, pairs, theta, rho, weight="length", status=None, integ="
     if rc:
         raise ValueError("bad arguments")
     return grad
+
+
+def fan_cubic(G, TH, a):
+    """Cubic refinement of a fan seed with bracket (a, a+1): the angle, or None
+    when the secant's linear interpolation stands."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    TH = np.ascontiguousarray(TH, dtype=np.float64)
+    out = np.zeros(1)
+    ok = lib().or_fan_cubic(_d(G), _d(TH), len(G), int(a), _d(out))
+    return float(out[0]) if ok else None
 
 
 def rayborn_rho(tof, freqs, resid):

@@ -611,6 +611,34 @@ typedef struct {
     int st;
 } FanSample;
 
+/* Cubic refinement of the fan seed: with the bracket (a, a+1) and both of its
+   outer neighbours sampled, and G strictly monotone over the four samples
+   a-1..a+2, the first linking angle is the value at G = 0 of the cubic that
+   interpolates theta as a function of G through those samples (inverse
+   Lagrange interpolation), if it lies strictly inside the bracket.  Otherwise
+   (returns 0) the secant's own linear interpolation of the bracket stands. */
+static int fan_cubic(const double *G, const double *TH, int m, int a, double *th)
+{
+    if (a < 1 || a + 2 > m - 1) return 0;
+    const double *g = G + a - 1, *t = TH + a - 1;
+    for (int i = 0; i < 4; i++)
+        if (!(g[i] == g[i])) return 0;
+    int up = g[1] > g[0];
+    for (int i = 0; i < 3; i++)
+        if (up ? !(g[i + 1] > g[i]) : !(g[i + 1] < g[i])) return 0;
+    double v = 0.0;
+    for (int i = 0; i < 4; i++) {
+        double w = 1.0;
+        for (int k = 0; k < 4; k++)
+            if (k != i) w *= (0.0 - g[k]) / (g[i] - g[k]);
+        v += w * t[i];
+    }
+    double lo = t[1] < t[2] ? t[1] : t[2], hi = t[1] < t[2] ? t[2] : t[1];
+    if (!(v > lo && v < hi)) return 0;
+    *th = v;
+    return 1;
+}
+
 static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, int rcv, const FanSample *row,
                      LinkOut *out)
 {
@@ -669,6 +697,8 @@ static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, in
         int far = near == found ? found + 1 : found;
         link_after_hit(&s, TH[far], G[far]);
         th = link_after_hit(&s, TH[near], G[near]);
+        double thc;
+        if (fan_cubic(G, TH, n - 1, found, &thc)) th = thc;
     } else if (own->st == ST_LINKED) {
         th = link_after_hit(&s, th_own, own->g);
     } else {
@@ -1008,4 +1038,11 @@ int or_rayborn_rho(int n, int n_freq, const double *T, const double *freqs, cons
         rho[i] = acc;
     }
     return 0;
+}
+
+/* The fan start's cubic refinement on its own (samples G[0..m-1], TH[0..m-1],
+   bracket (a, a+1)): returns 1 and the angle, or 0 when the linear seed stands. */
+int or_fan_cubic(const double *G, const double *TH, int m, int a, double *th)
+{
+    return fan_cubic(G, TH, m, a, th);
 }

@@ -195,6 +195,48 @@ __device__ __forceinline__ Sample<R> lookup(const Medium<R> &M, R uh, R du, R vh
     return o;
 }
 
+// ------------------------------------------------------ pipelined cell cache --
+// A wave that has its SIMD to itself (one lane per pair fills the chip at one
+// wave per SIMD) waits out every gather it issues, so a step does not look its
+// cells up when it needs them.  Three slots hold the cells of the stage points
+// (stage 1, stages 2-3, stage 4).  Right after a slot's last read in a step, the
+// cell of the matching stage point of the NEXT step is loaded into it without
+// waiting; that point is predicted from the state, the direction and the
+// curvature at the end of the previous step (x+ ~ x + ds d + ds^2/2 k, next
+// stage points ~ x+ + ds/2 d+ and x+ + ds d+ with d+ ~ d + ds k), all of which
+// are exact values, so a wrong guess never feeds the next guess.  The step reads
+// its samples from the slots without branching and records how far each stage
+// point lies from its slot's cell; a lane with a point outside (a missed
+// prediction, the first step of a ray, the clamped edge of the grid) redoes the
+// whole step from direct lookups.  Either way the samples are the bilinear
+// interpolation in the cell containing the point.
+template <class R>
+struct Slot {
+    R v[12];
+    R fx, fy;  // cell origin in grid coordinates
+    int ix, iy;
+};
+
+template <class R>
+__device__ __forceinline__ void slot_fetch(const Medium<R> &M, Slot<R> &c, R u, R v)
+{
+    // float->int truncation maps NaN to 0 and saturates: any position gives an
+    // in-bounds cell
+    c.ix = min(max((int)u, 0), M.nx - 2);
+    c.iy = min(max((int)v, 0), M.ny - 2);
+    c.fx = (R)c.ix;
+    c.fy = (R)c.iy;
+    load_cell(M.tab, __umul24((uint32_t)c.iy, (uint32_t)(M.nx - 1)) + (uint32_t)c.ix, c.v);
+}
+
+template <class R>
+__device__ __forceinline__ void interp(const R (&v)[12], R t, R s, Sample<R> &o)
+{
+    o.c = fma(s, fma(t, v[3], v[2]), fma(t, v[1], v[0]));
+    o.gx = fma(s, fma(t, v[7], v[6]), fma(t, v[5], v[4]));
+    o.gy = fma(s, fma(t, v[11], v[10]), fma(t, v[9], v[8]));
+}
+
 // dd/ds = -(G - (G.d) d) / c
 template <class R>
 __device__ __forceinline__ void curvature(const Sample<R> &S, R ic, R dx, R dy, R &kx, R &ky)
@@ -212,6 +254,7 @@ struct Ray {
     R uh, ul, vh, vl;
     R dxh, dxl, dyh, dyl;
     R Th, Tl;  // running trapezoid sum of w/c (pixels * s/m), compensated
+    R kx, ky;  // curvature dd/ds at the end of the last step (cell prediction only)
     int m;     // steps taken in this ray
 };
 
@@ -233,6 +276,7 @@ __device__ __forceinline__ void ray_start(Ray<R> &ray, double pu, double pv, dou
         ray.ul = ray.vl = ray.dxl = ray.dyl = (R)0;
     }
     ray.Th = ray.Tl = (R)0;
+    ray.kx = ray.ky = (R)0;
     ray.m = 0;
 }
 
@@ -252,28 +296,47 @@ __device__ __forceinline__ void materialize(R &x)
     asm volatile("" : "+v"(x));
 }
 
-template <class R, bool COMP, int INTEG>
-__device__ __forceinline__ StepOut<R> ray_step(const Medium<R> &M, const Ray<R> &y, Ray<R> &nxt, R ds)
+// Fills the slots for the first step of a ray starting at y, without waiting.
+template <class R>
+__device__ __forceinline__ void slots_prime(const Medium<R> &M, Slot<R> (&C)[3], const Ray<R> &y, R ds, int integ)
 {
-    StepOut<R> o;
+    const R dx = y.dxh + y.dxl, dy = y.dyh + y.dyl;
+    slot_fetch(M, C[0], y.uh + y.ul, y.vh + y.vl);
+    if (integ == 4) slot_fetch(M, C[1], y.uh + fma(ds * (R)0.5, dx, y.ul), y.vh + fma(ds * (R)0.5, dy, y.vl));
+    slot_fetch(M, C[2], y.uh + fma(ds, dx, y.ul), y.vh + fma(ds, dy, y.vl));
+}
+
+// The stage arithmetic of one step, reading its medium samples from `smp`
+// (slots or direct lookups): start sample and 1/c there, position and direction
+// increments, and the curvature at the last stage (kept for the next prediction).
+template <class R>
+struct StageOut {
+    Sample<R> s1;
+    R ic1, incx, incy, idx, idy, kx, ky;
+};
+
+template <class R, int INTEG, class S>
+__device__ __forceinline__ void stages(S &smp, const Ray<R> &y, R ds, StageOut<R> &o)
+{
     const R d1x = y.dxh + y.dxl, d1y = y.dyh + y.dyl;
-    R incx, incy, idx, idy;
     if (INTEG == 4) {
         // RK4 stage points: x, x + ds/2 d1, x + ds/2 d2, x + ds d3.  The first two
-        // depend only on the state and the last two only on k1 and k2, so the
-        // lookups go out in two dependent pairs: one step costs two memory
-        // round trips instead of four.
+        // depend only on the state and the last two only on k1 and k2, so direct
+        // lookups go out in two independent pairs.
         const R h2 = ds * (R)0.5;
-        o.s1 = lookup(M, y.uh, y.ul, y.vh, y.vl);
-        Sample<R> s2 = lookup(M, y.uh, fma(h2, d1x, y.ul), y.vh, fma(h2, d1y, y.vl));
+        o.s1 = smp.get(0, y.ul, y.vl);
+        Sample<R> s2 = smp.get(1, fma(h2, d1x, y.ul), fma(h2, d1y, y.vl));
+        smp.done(0);
         o.ic1 = rcp(o.s1.c);
         R k1x, k1y, k2x, k2y;
         curvature(o.s1, o.ic1, d1x, d1y, k1x, k1y);
         R d2x = fma(h2, k1x, d1x), d2y = fma(h2, k1y, d1y);
         curvature(s2, rcp(s2.c), d2x, d2y, k2x, k2y);
         R d3x = fma(h2, k2x, d1x), d3y = fma(h2, k2y, d1y);
-        Sample<R> s3 = lookup(M, y.uh, fma(h2, d2x, y.ul), y.vh, fma(h2, d2y, y.vl));
-        Sample<R> s4 = lookup(M, y.uh, fma(ds, d3x, y.ul), y.vh, fma(ds, d3y, y.vl));
+        Sample<R> s3 = smp.get(2, fma(h2, d2x, y.ul), fma(h2, d2y, y.vl));
+        Sample<R> s4 = smp.get(3, fma(ds, d3x, y.ul), fma(ds, d3y, y.vl));
+        smp.done(2);
+        smp.done(3);
         R k3x, k3y, k4x, k4y;
         curvature(s3, rcp(s3.c), d3x, d3y, k3x, k3y);
         R d4x = fma(ds, k3x, d1x), d4y = fma(ds, k3y, d1y);
@@ -282,14 +345,18 @@ __device__ __forceinline__ StepOut<R> ray_step(const Medium<R> &M, const Ray<R> 
         materialize(k4y);
         // x+ = x + ds/6 (d1 + 2 d2 + 2 d3 + d4) = x + ds d1 + ds^2/6 (k1 + k2 + k3)
         const R c6 = ds * ds * (R)(1.0 / 6.0), s6 = ds * (R)(1.0 / 6.0);
-        incx = fma(c6, k1x + k2x + k3x, ds * d1x);
-        incy = fma(c6, k1y + k2y + k3y, ds * d1y);
-        idx = s6 * (k1x + (R)2 * (k2x + k3x) + k4x);
-        idy = s6 * (k1y + (R)2 * (k2y + k3y) + k4y);
+        o.incx = fma(c6, k1x + k2x + k3x, ds * d1x);
+        o.incy = fma(c6, k1y + k2y + k3y, ds * d1y);
+        o.idx = s6 * (k1x + (R)2 * (k2x + k3x) + k4x);
+        o.idy = s6 * (k1y + (R)2 * (k2y + k3y) + k4y);
+        o.kx = k4x;
+        o.ky = k4y;
     } else {
-        // Heun stage points x and x + ds d1: both known up front, one round trip
-        o.s1 = lookup(M, y.uh, y.ul, y.vh, y.vl);
-        Sample<R> s2 = lookup(M, y.uh, fma(ds, d1x, y.ul), y.vh, fma(ds, d1y, y.vl));
+        // Heun stage points x and x + ds d1
+        o.s1 = smp.get(0, y.ul, y.vl);
+        Sample<R> s2 = smp.get(3, fma(ds, d1x, y.ul), fma(ds, d1y, y.vl));
+        smp.done(0);
+        smp.done(3);
         o.ic1 = rcp(o.s1.c);
         R k1x, k1y, k2x, k2y;
         curvature(o.s1, o.ic1, d1x, d1y, k1x, k1y);
@@ -298,11 +365,83 @@ __device__ __forceinline__ StepOut<R> ray_step(const Medium<R> &M, const Ray<R> 
         materialize(k2x);
         materialize(k2y);
         // x+ = x + ds/2 (d1 + d2) = x + ds d1 + ds^2/2 k1
-        incx = fma(ds * ds * (R)0.5, k1x, ds * d1x);
-        incy = fma(ds * ds * (R)0.5, k1y, ds * d1y);
-        idx = ds * (R)0.5 * (k1x + k2x);
-        idy = ds * (R)0.5 * (k1y + k2y);
+        o.incx = fma(ds * ds * (R)0.5, k1x, ds * d1x);
+        o.incy = fma(ds * ds * (R)0.5, k1y, ds * d1y);
+        o.idx = ds * (R)0.5 * (k1x + k2x);
+        o.idy = ds * (R)0.5 * (k1y + k2y);
+        o.kx = k2x;
+        o.ky = k2y;
     }
+}
+
+// Slot reads for the fast path.  Stage k (0..3; Heun uses 0 and 3) reads slot
+// 0, 1, 1, 2; done(k) reloads that slot for the next step.  With curvature k at
+// the state (x, d): x+ = x + ds d + ds^2/2 k, d+ = d + ds k, so the next RK4
+// stage points are x+, x+ + ds/2 d+ (+ ds^2/4 k at stage 3; the shared slot
+// aims between), and x+ + ds (d+ + ds/2 k); Heun's are x+ and x+ + ds d+.
+template <class R, int INTEG>
+struct SlotSampler {
+    const Medium<R> &M;
+    Slot<R> (&C)[3];
+    R uh, ul, vh, vl, dx, dy, kx, ky, ds, dev;
+    __device__ __forceinline__ Sample<R> get(int k, R du, R dv)
+    {
+        const Slot<R> &c = C[k == 0 ? 0 : k == 3 ? 2 : 1];
+        Sample<R> o;
+        o.t = (uh - c.fx) + du;
+        o.s = (vh - c.fy) + dv;
+        dev = fmax_(dev, fmax_(fabs(o.t - (R)0.5), fabs(o.s - (R)0.5)));
+        o.ix = c.ix;
+        o.iy = c.iy;
+        interp(c.v, o.t, o.s, o);
+        return o;
+    }
+    __device__ __forceinline__ void fetch(Slot<R> &c, R a, R b)
+    {
+        const R hh = ds * ds;
+        slot_fetch(M, c, uh + fma(a * ds, dx, fma(b * hh, kx, ul)), vh + fma(a * ds, dy, fma(b * hh, ky, vl)));
+    }
+    // (the scheduling barrier keeps the compiler from sinking the loads to the
+    // end of the step, which would shorten the time they have to arrive)
+    __device__ __forceinline__ void done(int k)
+    {
+        if (k == 0) fetch(C[0], (R)1, (R)0.5);
+        if (INTEG == 4) {
+            if (k == 2) fetch(C[1], (R)1.5, (R)1.125);
+            if (k == 3) fetch(C[2], (R)2, (R)2);
+        } else {
+            if (k == 3) fetch(C[2], (R)2, (R)1.5);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+};
+
+// Direct lookups: the recovery path of a step with a point outside its slot.
+template <class R>
+struct LookupSampler {
+    const Medium<R> &M;
+    R uh, vh;
+    __device__ __forceinline__ Sample<R> get(int, R du, R dv) { return lookup(M, uh, du, vh, dv); }
+    __device__ __forceinline__ void done(int) {}
+};
+
+template <class R, bool COMP, int INTEG>
+__device__ __forceinline__ StepOut<R> ray_step(const Medium<R> &M, Slot<R> (&C)[3], const Ray<R> &y, Ray<R> &nxt,
+                                               R ds)
+{
+    StageOut<R> st;
+    SlotSampler<R, INTEG> fs{M, C, y.uh, y.ul, y.vh, y.vl, y.dxh + y.dxl, y.dyh + y.dyl, y.kx, y.ky, ds, (R)0};
+    stages<R, INTEG>(fs, y, ds, st);
+    if (!(fs.dev < (R)0.5)) {
+        LookupSampler<R> ls{M, y.uh, y.vh};
+        stages<R, INTEG>(ls, y, ds, st);
+    }
+    StepOut<R> o;
+    o.s1 = st.s1;
+    o.ic1 = st.ic1;
+    const R incx = st.incx, incy = st.incy, idx = st.idx, idy = st.idy;
+    nxt.kx = st.kx;
+    nxt.ky = st.ky;
     if (COMP) {
         R s, e;
         // inside the ring a grid coordinate is at least max(1, ds) (the plan's
@@ -471,7 +610,8 @@ __device__ __forceinline__ double link_next_hit(Link &L, double g)
 // the receiver's misfit over consecutive samples seeds its secant.
 struct FanSeed {
     double th_far, g_far, th_near, g_near;  // bracket ends (larger |g| first)
-    int found;
+    double th_first;                        // first linking angle (cubic), if `cubic`
+    int found, cubic;
 };
 
 constexpr uint32_t kStraight = 1u << 16;  // internal: fixed pass at straight angles
@@ -612,6 +752,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
     unsigned long long n_steps = 0, n_rays = 0;
 
     Ray<R> ray;
+    Slot<R> C[3];
     Link L;
     int e = 0, r = 0;
     double pe = 0, dr = 0;  // emitter angle, receiver offset mod 2pi
@@ -666,6 +807,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
                         link_next_hit(L, sd.g_far);
                         L.th = sd.th_near;
                         th = link_next_hit(L, sd.g_near);
+                        if (sd.cubic) th = sd.th_first;
                     } else if (st0 == RTX_RAY_LINKED) {
                         th = link_next_hit(L, a.f_g[q]);
                     } else {
@@ -681,6 +823,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
                     }
                 }
                 start_ray<R, COMP>(ray, gg, e, th);
+                slots_prime(m, C, ray, ds, INTEG);
                 active = true;
                 return;
             }
@@ -695,7 +838,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
 
     while (active) {
         Ray<R> nxt;
-        StepOut<R> so = ray_step<R, COMP, INTEG>(m, ray, nxt, ds);
+        StepOut<R> so = ray_step<R, COMP, INTEG>(m, C, ray, nxt, ds);
         n_steps++;
         const R w_start = ray.m == 0 ? ds * (R)0.5 : ds;
         const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
@@ -770,6 +913,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
             if (!pair_done) {
                 L.th = th_next;
                 start_ray<R, COMP>(ray, gg, e, th_next);
+                slots_prime(m, C, ray, ds, INTEG);
             }
         }
         if (pair_done) {
@@ -854,6 +998,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
     R ds = (R)gg.ds, R2 = (R)(gg.R * gg.R), cx = (R)gg.cx, cy = (R)gg.cy;
     unsigned long long n_steps = 0, n_rays = 0;
     Ray<R> ray;
+    Slot<R> C[3];
     CellAcc<R> acc;
     acc.n0 = -1;
     acc.a[0] = acc.a[1] = acc.a[2] = acc.a[3] = (R)0;
@@ -885,6 +1030,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
             double rho = ok ? a.rho[q] : 0.0;
             if (ok && rho != 0.0) {
                 start_ray<R, COMP>(ray, gg, e, a.theta[q]);
+                slots_prime(m, C, ray, ds, INTEG);
                 scale = (R)(rho * gg.h);
                 active = true;
                 return;
@@ -898,7 +1044,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
 
     while (active) {
         Ray<R> nxt;
-        StepOut<R> so = ray_step<R, COMP, INTEG>(m, ray, nxt, ds);
+        StepOut<R> so = ray_step<R, COMP, INTEG>(m, C, ray, nxt, ds);
         n_steps++;
         const R kap = a.weight == RTX_W_DTDC ? -so.ic1 * so.ic1 : (R)1;
         const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
@@ -949,7 +1095,17 @@ __global__ void k_batch_reset(const int64_t *__restrict__ off, int n_inst, unsig
 // One block per emitter e (all ordered pairs in canonical order): samples
 // G_j = H_j - D_r of the straight rays at offsets j = 1..n-1 with
 // H_j = g_j + D_j; each receiver takes the sign change over consecutive samples
-// nearest to its own offset, searched outward (own, own+1, own-1-1, ...).
+// nearest to its own offset, searched outward (own, own+1, own-1-1, ...).  With
+// both outer neighbours of the bracket sampled and G strictly monotone over the
+// four samples, the first linking angle is the zero of the cubic interpolating
+// theta as a function of G through them (inverse Lagrange interpolation), if it
+// falls strictly inside the bracket; else the secant's linear interpolation.
+__device__ __forceinline__ double fan_straight(const Geo &g, int e, int j)
+{
+    int k = (e + j) % g.n_elem;
+    return (mod2pi(elem_angle(g, k) - elem_angle(g, e)) - kPi) / 2.0;
+}
+
 __global__ void __launch_bounds__(kBlock) k_fan_seed(Geo g, const double *__restrict__ f_g,
                                                      const int8_t *__restrict__ f_st, FanSeed *__restrict__ seed)
 {
@@ -982,7 +1138,33 @@ __global__ void __launch_bounds__(kBlock) k_fan_seed(Geo g, const double *__rest
         }
         FanSeed sd;
         sd.found = found >= 0;
-        sd.th_far = sd.g_far = sd.th_near = sd.g_near = 0.0;
+        sd.cubic = 0;
+        sd.th_far = sd.g_far = sd.th_near = sd.g_near = sd.th_first = 0.0;
+        if (found >= 1 && found + 2 <= n - 2) {
+            double gg[4], tt[4];
+            bool ok = true;
+            for (int q = 0; q < 4; q++) {
+                gg[q] = H[found - 1 + q] - Dr;
+                tt[q] = fan_straight(g, e, found + q);  // offset (found - 1 + q) + 1
+                ok = ok && gg[q] == gg[q];
+            }
+            const bool up = gg[1] > gg[0];
+            for (int q = 0; q < 3; q++) ok = ok && (up ? gg[q + 1] > gg[q] : gg[q + 1] < gg[q]);
+            if (ok) {
+                double v = 0.0;
+                for (int q = 0; q < 4; q++) {
+                    double w = 1.0;
+                    for (int m = 0; m < 4; m++)
+                        if (m != q) w *= (0.0 - gg[m]) / (gg[q] - gg[m]);
+                    v += w * tt[q];
+                }
+                const double lo = fmin(tt[1], tt[2]), hi = fmax(tt[1], tt[2]);
+                if (v > lo && v < hi) {
+                    sd.cubic = 1;
+                    sd.th_first = v;
+                }
+            }
+        }
         if (found >= 0) {
             double ga = H[found] - Dr, gb = H[found + 1] - Dr;
             int nr = fabs(ga) <= fabs(gb) ? found : found + 1;
@@ -1071,6 +1253,7 @@ __global__ void __launch_bounds__(kBlock) k_weights(Medium<R> M, Geo g, WArgs A)
     const R cx = (R)g.cx, cy = (R)g.cy;
     const R hh = (R)g.h;
     Ray<R> ray;
+    Slot<R> C[3];
     RowSink<R, FILL> sink;
     sink.cols = A.cols;
     sink.vals = (R *)A.vals;
@@ -1100,6 +1283,7 @@ __global__ void __launch_bounds__(kBlock) k_weights(Medium<R> M, Geo g, WArgs A)
             begin_row();
             if (ok) {
                 start_ray<R, COMP>(ray, g, e, A.theta[p]);
+                slots_prime(M, C, ray, ds, INTEG);
                 active = true;
                 return;
             }
@@ -1112,7 +1296,7 @@ __global__ void __launch_bounds__(kBlock) k_weights(Medium<R> M, Geo g, WArgs A)
 
     while (active) {
         Ray<R> nxt;
-        StepOut<R> so = ray_step<R, COMP, INTEG>(M, ray, nxt, ds);
+        StepOut<R> so = ray_step<R, COMP, INTEG>(M, C, ray, nxt, ds);
         const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
         R pu = (nxt.uh - cx) + nxt.ul, pv = (nxt.vh - cy) + nxt.vl;
         const bool crossed = !bad && (pu * pu + pv * pv >= R2);

@@ -90,15 +90,33 @@ def test_c4_full_size(rtx, tmp_path):
     print(f"ray-Born adjoint: |g - g_ref| / |g_abs| = {err:.2e}, |g_ref| / |g_abs| = "
           f"{np.linalg.norm(gref) / np.linalg.norm(gabs):.2e}", flush=True)
     assert err < 1e-4, err
-    # the FP64 path on the same angles reproduces the oracle's adjoint exactly
+    # The FP64 path on the same angles: travel time within the FP64 bound of
+    # 1e-10.  The striped rows (80 m/s between adjacent node rows) make the
+    # fixed-angle path ill-conditioned: a relative change of 1e-13 in the launch
+    # angles moves the oracle's own adjoint by ~4e-10 of the sum of absolute
+    # contributions (and T by ~7e-11), and the two FP64 implementations round
+    # differently in every step (the GPU fuses multiply-adds).  The adjoint bar
+    # is therefore 20x the oracle's own change under that perturbation.
     p64 = rtx.Plan(cfg["nx"], cfg["ny"], cfg["h"], *ring, prec="f64", max_pairs=len(sub))
     s64 = sub[:512]
-    f64 = p64.trace(cd, pairs=_dev(pairs[s64].astype(np.int32)), theta=_dev(th[s64]), fixed=True)
-    r64 = _dev(rho[:512])
-    g64 = p64.adjoint(f64["theta"], f64["status"], r64, pairs=_dev(pairs[s64].astype(np.int32)))
+    p64d = _dev(pairs[s64].astype(np.int32))
+    f64 = p64.trace(cd, pairs=p64d, theta=_dev(th[s64]), fixed=True)
     st64 = f64["status"].cpu().numpy()
-    gref64 = oracle.adjoint(c, cfg["h"], ring, pairs[s64], th[s64], rho[:512], status=st64)
-    assert np.linalg.norm(g64.cpu().numpy() - gref64) / np.linalg.norm(gref64) < 1e-10
+    chk64 = oracle.trace(oracle.grid_medium(c, cfg["h"]), ring, pairs[s64], theta=th[s64], fixed=True)
+    assert np.array_equal(st64, chk64["status"])
+    ok64 = st64 == oracle.LINKED
+    t_err64 = np.abs(f64["tof"].cpu().numpy()[ok64] / chk64["tof"][ok64] - 1).max()
+    r64 = rho[:512]
+    g64 = p64.adjoint(f64["theta"], f64["status"], _dev(r64), pairs=p64d).cpu().numpy()
+    gref64 = oracle.adjoint(c, cfg["h"], ring, pairs[s64], th[s64], r64, status=st64)
+    gabs64 = oracle.adjoint(c, cfg["h"], ring, pairs[s64], th[s64], np.abs(r64), status=st64)
+    gper64 = oracle.adjoint(c, cfg["h"], ring, pairs[s64], th[s64] * (1 + 1e-13), r64, status=st64)
+    band = np.linalg.norm(gper64 - gref64) / np.linalg.norm(gabs64)
+    a_err64 = np.linalg.norm(g64 - gref64) / np.linalg.norm(gabs64)
+    print(f"FP64 subset: T rel {t_err64:.2e}; adjoint {a_err64:.2e} of |g_abs| (oracle's own change under a "
+          f"1e-13 angle perturbation: {band:.2e})", flush=True)
+    assert t_err64 < 1e-10
+    assert a_err64 < max(20 * band, 1e-10)
     p64.close()
     # all pairs: finite, and linear in the residual
     r_all = synth.complex_residual(n, cfg["n_freq"], cfg["resid_seed"])

@@ -38,6 +38,12 @@ MUTATIONS = {
                                  "w[2] = (-3.0 * t * t * t - 3.0 * t * t + 3.0 * t + 1.0) / 6.0;"),
     "bspline_derivative_sign": ("dw[0] = -u * u / 2.0;", "dw[0] = u * u / 2.0;"),
     "bspline_half_sample_mirror": ("if (i < 0) return -i;", "if (i < 0) return -i - 1;"),
+    "fan_cubic_weight_sign": ("if (k != i) w *= (0.0 - g[k]) / (g[i] - g[k]);",
+                              "if (k != i) w *= (0.0 + g[k]) / (g[i] - g[k]);"),
+    "fan_cubic_shifted_stencil": ("const double *g = G + a - 1, *t = TH + a - 1;",
+                                  "const double *g = G + a - 1, *t = TH + a;"),
+    "fan_cubic_bracket_ends": ("double lo = t[1] < t[2] ? t[1] : t[2], hi = t[1] < t[2] ? t[2] : t[1];",
+                               "double lo = t[0] < t[3] ? t[0] : t[3], hi = t[0] < t[3] ? t[3] : t[0];"),
     "fan_target_wrong_receiver": ("G[j - 1] = row[j - 1].st == ST_LINKED ? (row[j - 1].g + Dj) - Dr : NAN;",
                                   "G[j - 1] = row[j - 1].st == ST_LINKED ? row[j - 1].g - Dr : NAN;"),
 }
@@ -61,6 +67,9 @@ PINS = [
     lambda o: P.test_adjoint_is_transpose_of_weights(o),
     lambda o: P.test_dtdc_adjoint_matches_finite_differences(o),
     lambda o: P.test_rayborn_rho_is_derivative_of_phase_data(o),
+    lambda o: P.test_fan_cubic_exact_for_cubic_inverse(o),
+    lambda o: P.test_fan_cubic_fourth_order_on_smooth_inverse(o),
+    lambda o: P.test_fan_cubic_falls_back(o),
     lambda o: P.test_fan_start_same_roots_fewer_rays(o),
     lambda o: P.test_fan_start_fisheye_reversed_orientation(o),
 ]

@@ -504,3 +504,60 @@ def test_fan_start_fisheye_reversed_orientation(orc):
     assert np.all(b["status"] == orc.LINKED)
     assert np.abs(a["tof"] / b["tof"] - 1).max() < 1e-5
     assert b["n_marches"].mean() < a["n_marches"].mean()
+
+
+# ------------------------------------------------- fan start: cubic refinement --
+def test_fan_cubic_exact_for_cubic_inverse(orc):
+    """When theta is a cubic polynomial of G, the refinement returns its value
+    at G = 0 (inverse interpolation through four samples is then exact)."""
+    p = np.array([0.013, -0.7, 0.4, 2.5])  # theta(G) = p0 + p1 G + p2 G^2 + p3 G^3
+    G = np.array([-0.21, -0.12, -0.05, 0.03, 0.11, 0.2])
+    TH = p[0] + p[1] * G + p[2] * G ** 2 + p[3] * G ** 3
+    a = 2  # bracket (G[2] < 0 < G[3])
+    th = orc.fan_cubic(G, TH, a)
+    assert th is not None and abs(th - p[0]) < 1e-15
+    # decreasing samples (the fish-eye's reversed orientation) work the same way
+    th2 = orc.fan_cubic(G[::-1], TH[::-1], len(G) - 2 - a)
+    assert th2 is not None and abs(th2 - p[0]) < 1e-15
+
+
+def test_fan_cubic_fourth_order_on_smooth_inverse(orc):
+    """G(theta) = tan(theta - 0.1) + 0.3 (theta - 0.1)^2 sampled on a uniform fan
+    of spacing d: the error of the refinement falls as d^4, the linear
+    interpolation's as d^2."""
+    root = 0.1
+
+    def G(t):
+        return np.tan(t - root) + 0.3 * (t - root) ** 2
+
+    errs_c, errs_l = [], []
+    for d in (0.04, 0.02, 0.01):
+        TH = root - 0.37 * d + d * np.arange(-3, 4)  # root inside the bracket (3, 4)
+        g = G(TH)
+        a = 3
+        th = orc.fan_cubic(g, TH, a)
+        lin = TH[a] - g[a] * (TH[a + 1] - TH[a]) / (g[a + 1] - g[a])
+        errs_c.append(abs(th - root))
+        errs_l.append(abs(lin - root))
+    for k in range(2):
+        assert 12 < errs_c[k] / errs_c[k + 1] < 20
+        assert 3 < errs_l[k] / errs_l[k + 1] < 5
+    assert errs_c[-1] < 1e-3 * errs_l[-1]
+
+
+def test_fan_cubic_falls_back(orc):
+    TH = np.linspace(-0.1, 0.1, 6)
+    good = np.array([-0.3, -0.2, -0.05, 0.06, 0.2, 0.31])
+    assert orc.fan_cubic(good, TH, 2) is not None
+    assert orc.fan_cubic(good, TH, 0) is None  # no outer neighbour below
+    assert orc.fan_cubic(good, TH, 4) is None  # none above
+    bump = good.copy()
+    bump[1] = -0.01  # not monotone over samples 1..4
+    assert orc.fan_cubic(bump, TH, 2) is None
+    nan = good.copy()
+    nan[4] = np.nan  # an outer ray that did not hit
+    assert orc.fan_cubic(nan, TH, 2) is None
+    # strongly curved samples whose cubic root leaves the bracket
+    far = np.array([-1.0, -0.999, -1e-9, 1.0, 1.0001, 1.0002])
+    r = orc.fan_cubic(far, TH, 2)
+    assert r is None or TH[2] < r < TH[3]
