@@ -169,7 +169,10 @@ int rtx_tof_forward(rtx_plan plan, const double *c, const int32_t *pairs, int64_
    selects the pairs used: those whose status is LINKED or NOT_CONVERGED, i.e.
    whose theta is a traced ray that reached the ring; others are skipped.  grad: [ny][nx] float (RTX_F32C) or double
    (RTX_F64), accumulated into (the caller zeroes it).  Accumulation uses
-   atomics, so the FP32 result depends on summation order at rounding level. */
+   atomics, so the FP32 result depends on summation order at rounding level.
+   Node updates pass through a bounded queue in on-chip memory; if one of its
+   waits ever hits its bound, the gradient is incomplete and the next
+   rtx_plan_stats call on the plan returns RTX_E_HIP. */
 int rtx_tof_adjoint(rtx_plan plan, const double *c, const int32_t *pairs, int64_t n_pairs,
                     const double *theta, const int8_t *status, const double *tof, const void *resid,
                     int32_t resid_kind, const double *freqs_hz, int32_t n_freq, int32_t weight, void *grad,
@@ -177,7 +180,8 @@ int rtx_tof_adjoint(rtx_plan plan, const double *c, const int32_t *pairs, int64_
 
 /* Work counters of the last trace / adjoint call on this plan (synchronises the
    device): total RK steps marched and rays traced (both trace passes of a fan
-   start), and adjoint steps. */
+   start), and adjoint steps.  Returns RTX_E_HIP (and still fills the counters)
+   if an adjoint of this plan reported an incomplete gradient. */
 int rtx_plan_stats(rtx_plan plan, int64_t *trace_steps, int64_t *trace_rays, int64_t *adjoint_steps);
 
 /* Work counters of one kernel launch of the last call: region 0 = the trace
@@ -226,7 +230,10 @@ typedef struct rtx_batch_s *rtx_batch;
 
 /* Validates every instance (as rtx_plan_create does), allocates the packed
    tables and per-instance descriptors.  weight: rtx_weight of the adjoint.
-   rays_per_block: 0 (default 256), 64, 128 or 256.  inst is (host) [n_inst]. */
+   rays_per_block: 0 (default 256), 64, 128 or 256.  inst is (host) [n_inst].
+   A batch holds at most 255 instances (else RTX_E_UNSUPPORTED) whose grids
+   hold at most 2^24 nodes each (else RTX_E_ARG): the adjoint tags each node
+   update with its instance in 8 bits. */
 int rtx_batch_create(rtx_batch *out, const rtx_opts *opts, int32_t weight, int32_t rays_per_block,
                      int32_t n_inst, const rtx_instance *inst);
 
@@ -236,7 +243,8 @@ int rtx_batch_run(rtx_batch batch, void *stream);
 /* Per-instance completion of the last run (synchronises the device), in ms from
    the start of the run, from the device wall clock: fwd_ms when the instance's
    last pair was linked, done_ms when its last adjoint ray finished (= fwd_ms
-   without adjoint).  Both (host) [n_inst], either may be NULL. */
+   without adjoint).  Both (host) [n_inst], either may be NULL.  Returns
+   RTX_E_HIP if the batch's adjoint reported incomplete gradients. */
 int rtx_batch_times(rtx_batch batch, double *fwd_ms, double *done_ms);
 
 /* Frees the batch (synchronises the device first). */

@@ -109,7 +109,14 @@ __global__ void k_pack(const double *__restrict__ c, int nx, int ny, R *__restri
 
 // -------------------------------------------------------------- arithmetic --
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+// FP64: hardware reciprocal refined by two Newton steps (within an ulp of 1/x;
+// a correctly rounded division costs twice the instructions)
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
 __device__ __forceinline__ float floor_(float x) { return floorf(x); }
 __device__ __forceinline__ double floor_(double x) { return floor(x); }
 __device__ __forceinline__ float fmin_(float a, float b) { return fminf(a, b); }
@@ -142,10 +149,18 @@ struct Medium {
 };
 
 // Cells are addressed with 32-bit byte offsets from the table base (tables are
-// far below 4 GiB), so the loads take the scalar-base + 32-bit offset form.
+// far below 4 GiB), so the loads take the scalar-base + 32-bit offset form.  The
+// base is cast to the global address space: a table pointer read from memory (a
+// batch's instance record) would otherwise be dereferenced with flat loads.
+// (the host-side parse of these device functions sees no address spaces)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLOBAL_AS __attribute__((address_space(1)))
+#else
+#define GLOBAL_AS
+#endif
 __device__ __forceinline__ void load_cell(const float *tab, uint32_t cell, float (&v)[12])
 {
-    const float4 *p = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tab) + __umul24(cell, 48u));
+    const GLOBAL_AS float4 *p = (const GLOBAL_AS float4 *)((const GLOBAL_AS char *)tab + __umul24(cell, 48u));
     float4 a = p[0], b = p[1], c = p[2];
     v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w;
     v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
@@ -154,7 +169,7 @@ __device__ __forceinline__ void load_cell(const float *tab, uint32_t cell, float
 
 __device__ __forceinline__ void load_cell(const double *tab, uint32_t cell, double (&v)[12])
 {
-    const double2 *p = reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(tab) + __umul24(cell, 96u));
+    const GLOBAL_AS double2 *p = (const GLOBAL_AS double2 *)((const GLOBAL_AS char *)tab + __umul24(cell, 96u));
     for (int k = 0; k < 6; k++) {
         double2 a = p[k];
         v[2 * k] = a.x;
@@ -220,13 +235,14 @@ struct Slot {
 template <class R>
 __device__ __forceinline__ void slot_fetch(const Medium<R> &M, Slot<R> &c, R u, R v)
 {
-    // float->int truncation maps NaN to 0 and saturates: any position gives an
-    // in-bounds cell
-    c.ix = min(max((int)u, 0), M.nx - 2);
-    c.iy = min(max((int)v, 0), M.ny - 2);
-    c.fx = (R)c.ix;
-    c.fy = (R)c.iy;
-    load_cell(M.tab, __umul24((uint32_t)c.iy, (uint32_t)(M.nx - 1)) + (uint32_t)c.ix, c.v);
+    // the cell origin is clamped to the grid in floating point (max/min return
+    // the number when the other operand is NaN), and the cell index
+    // fy (nx - 1) + fx is exact in the slot's precision (cells stay below 2^24)
+    c.fx = fmin_(fmax_(floor_(u), (R)0), (R)(M.nx - 2));
+    c.fy = fmin_(fmax_(floor_(v), (R)0), (R)(M.ny - 2));
+    c.ix = (int)c.fx;
+    c.iy = (int)c.fy;
+    load_cell(M.tab, (uint32_t)fma(c.fy, (R)(M.nx - 1), c.fx), c.v);
 }
 
 template <class R>
@@ -507,8 +523,15 @@ __device__ __forceinline__ double elem_angle(const Geo &g, int k)
     return g.phi0 + 2.0 * kPi * k / g.n_elem;
 }
 
+// a mod 2 pi in [0, 2 pi).  The arguments met here lie in (-2 pi, 4 pi), where
+// the result is a, a + 2 pi or a - 2 pi (the last exact): the same values as
+// fmod followed by adding 2 pi to a negative remainder, without fmod's
+// exponent-reduction loop.
 __device__ __forceinline__ double mod2pi(double a)
 {
+    if (a >= 0.0 && a < kTwoPi) return a;
+    if (a < 0.0 && a >= -kTwoPi) return a + kTwoPi;
+    if (a >= kTwoPi && a < 2.0 * kTwoPi) return a - kTwoPi;
     double r = fmod(a, kTwoPi);
     if (r < 0) r += kTwoPi;
     return r;
@@ -656,18 +679,33 @@ __device__ __forceinline__ void write_pair(const TraceArgs &A, int64_t p, double
     A.status[p] = (int8_t)st;
 }
 
-template <class R, bool COMP>
-__device__ __forceinline__ void start_ray(Ray<R> &ray, const Geo &g, int e, double th)
+// Emitter of a pair: its angle and ring-centred position (pixels), computed once
+// per pair; every ray of the pair starts there.
+struct Emitter {
+    double pe, ex, ey;
+};
+
+__device__ __forceinline__ Emitter emitter_of(const Geo &g, int e)
 {
-    double pe = elem_angle(g, e);
-    double ex = g.R * cos(pe), ey = g.R * sin(pe);
-    ray_start<R, COMP>(ray, ex + g.cx, ey + g.cy, pe + kPi + th);
+    Emitter o;
+    o.pe = elem_angle(g, e);
+    double sp, cp;
+    sincos(o.pe, &sp, &cp);
+    o.ex = g.R * cp;
+    o.ey = g.R * sp;
+    return o;
+}
+
+template <class R, bool COMP>
+__device__ __forceinline__ void start_ray(Ray<R> &ray, const Geo &g, const Emitter &em, double th)
+{
+    ray_start<R, COMP>(ray, em.ex + g.cx, em.ey + g.cy, em.pe + kPi + th);
 }
 
 // Sum of per-lane counters over the block, written to out[blockIdx.x].
 __device__ void block_sum2(unsigned long long a, unsigned long long b, unsigned long long *out)
 {
-    __shared__ unsigned long long sa[kBlock / 64], sb[kBlock / 64];
+    __shared__ unsigned long long sa[kBlock / 64 + 1], sb[kBlock / 64 + 1];
     for (int o = 32; o > 0; o >>= 1) {
         a += __shfl_xor(a, o);
         b += __shfl_xor(b, o);
@@ -698,7 +736,43 @@ struct AdjArgs {
     int weight;
     int max_steps;
     unsigned long long *stats;
+    unsigned int *err;  // set (bit 0) when an LDS queue wait hits its bound
+    // all ordered pairs (pairs == NULL, tile > 0): work items walk tile x tile
+    // blocks of (emitter, receiver) clusters of adjacent elements, so the rays
+    // of a wave run side by side from one cluster to another and their node
+    // updates land on fewer distinct nodes at a time (measured on the 256x256
+    // workload: adjoint 1.80 -> 1.44 ms; the same order made the forward
+    // passes slower, so they keep the canonical order); n_items counts the
+    // items, including the e == r and past-the-end slots they skip
+    int tile;
+    int64_t n_items;
 };
+
+// Work item of an all-pairs tile walk -> (e, r) and the canonical pair index.
+// Returns false for an item without a pair (e == r, or past the last element).
+__device__ __forceinline__ bool tile_item(int n, int t, int64_t item, int &e, int &r, int64_t &q)
+{
+    const int nc = (n + t - 1) / t;
+    const int64_t tt = item / (t * t);
+    const int l = (int)(item - tt * t * t);
+    e = (int)(tt / nc) * t + l / t;
+    r = (int)(tt % nc) * t + l % t;
+    if (e >= n || r >= n || e == r) return false;
+    q = (int64_t)e * (n - 1) + (r < e ? r : r - 1);
+    return true;
+}
+
+// Work item -> pair of the adjoint (false: no pair).
+__device__ __forceinline__ bool adj_item(const AdjArgs &a, const Geo &g, int64_t item, int &e, int &r, int64_t &q)
+{
+    if (a.pairs || a.tile == 0) {
+        TraceArgs pa;
+        pa.pairs = a.pairs;
+        q = item;
+        return pair_of(pa, g, item, e, r);
+    }
+    return tile_item(g.n_elem, a.tile, item, e, r, q);
+}
 
 // One problem of a batch (device copy).
 template <class R>
@@ -755,7 +829,8 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
     Slot<R> C[3];
     Link L;
     int e = 0, r = 0;
-    double pe = 0, dr = 0;  // emitter angle, receiver offset mod 2pi
+    Emitter em{};
+    double dr = 0;  // receiver angle relative to the emitter, mod 2 pi
     bool active = false;
 
     // Takes pairs from p onward until one is valid (invalid ones are written).
@@ -776,8 +851,8 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
                 q = p;
             }
             if (pair_of(a, gg, q, e, r)) {
-                pe = elem_angle(gg, e);
-                dr = mod2pi(elem_angle(gg, r) - pe);
+                em = emitter_of(gg, e);
+                dr = mod2pi(elem_angle(gg, r) - em.pe);
                 const bool given = (a.flags & (RTX_WARM_START | RTX_FIXED_ANGLE)) && !(a.flags & kStraight);
                 double th0 = given ? a.theta[q] : (dr - kPi) / 2.0;
                 link_reset(L, th0);
@@ -822,7 +897,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
                         goto next;
                     }
                 }
-                start_ray<R, COMP>(ray, gg, e, th);
+                start_ray<R, COMP>(ray, gg, em, th);
                 slots_prime(m, C, ray, ds, INTEG);
                 active = true;
                 return;
@@ -872,7 +947,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
                              0.5 * dsp * (double)rcp(sq.c);
                 T = acc * gg.h;
                 Lm = (ray.m * gg.ds + dsp) * gg.h;
-                g_mis = mod2pi(atan2(hit.qy, hit.qx) - pe) - dr;
+                g_mis = mod2pi(atan2(hit.qy, hit.qx) - em.pe) - dr;
                 st = RTX_RAY_LINKED;
             }
         }
@@ -912,7 +987,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
             }
             if (!pair_done) {
                 L.th = th_next;
-                start_ray<R, COMP>(ray, gg, e, th_next);
+                start_ray<R, COMP>(ray, gg, em, th_next);
                 slots_prime(m, C, ray, ds, INTEG);
             }
         }
@@ -928,54 +1003,100 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
 // ---------------------------------------------------------- adjoint kernel --
 
 
-// Pending hat weights of the current cell's four nodes.  Consecutive samples
-// of a ray in the same cell add into registers; when the ray moves to another
-// cell, the nodes it shares with the new cell keep their pending sums and only
-// the others are flushed with atomics (two per edge crossing, three per corner
-// crossing, instead of four per visit).
+// Pending hat weights of the current cell's four nodes: a[0] = (ix, iy),
+// a[1] = (ix+1, iy), a[2] = (ix, iy+1), a[3] = (ix+1, iy+1).  Consecutive
+// samples of a ray in one cell add into registers.  When the ray moves to an
+// adjacent cell the accumulator shifts by a column and/or a row: the two nodes
+// of the edge it leaves behind are emitted and the shared ones keep their sums
+// (two node updates per edge crossing, three per corner crossing).  Node
+// indices are 32-bit (grids stay below 2^24 cells).
 template <class R>
 struct CellAcc {
-    int64_t n0;  // node index of the cell's lower-left corner, -1 = empty
-    R a[4];      // nodes n0, n0 + 1, n0 + nx, n0 + nx + 1
+    int ix, iy;  // current cell; ix < 0: empty
+    R a[4];
+};
+
+// Up to four node updates produced by one accumulator operation.
+template <class R>
+struct Emit {
+    int n[4];
+    R v[4];
+    unsigned mask;  // bit k: entry k is valid
 };
 
 template <class R>
-__device__ __forceinline__ void acc_flush(R *grad, int nx, CellAcc<R> &A)
+__device__ __forceinline__ void acc_flush(int nx, CellAcc<R> &A, Emit<R> &E)
 {
-    if (A.n0 >= 0) {
-        unsafeAtomicAdd(grad + A.n0, A.a[0]);
-        unsafeAtomicAdd(grad + A.n0 + 1, A.a[1]);
-        unsafeAtomicAdd(grad + A.n0 + nx, A.a[2]);
-        unsafeAtomicAdd(grad + A.n0 + nx + 1, A.a[3]);
+    if (A.ix >= 0) {
+        const int n0 = A.iy * nx + A.ix;
+        E.n[0] = n0;
+        E.n[1] = n0 + 1;
+        E.n[2] = n0 + nx;
+        E.n[3] = n0 + nx + 1;
+        for (int k = 0; k < 4; k++) E.v[k] = A.a[k];
+        E.mask = 0xfu;
     }
-    A.n0 = -1;
+    A.ix = -1;
     A.a[0] = A.a[1] = A.a[2] = A.a[3] = (R)0;
 }
 
 template <class R>
-__device__ __forceinline__ void acc_move(R *grad, int nx, CellAcc<R> &A, int64_t n0)
+__device__ __forceinline__ void acc_move(int nx, CellAcc<R> &A, int ix, int iy, Emit<R> &E)
 {
-    R b[4] = {(R)0, (R)0, (R)0, (R)0};
-    if (A.n0 >= 0) {
-        const int64_t old[4] = {A.n0, A.n0 + 1, A.n0 + nx, A.n0 + nx + 1};
-        for (int k = 0; k < 4; k++) {
-            int64_t d = old[k] - n0;
-            int slot = d == 0 ? 0 : d == 1 ? 1 : d == nx ? 2 : d == nx + 1 ? 3 : -1;
-            if (slot >= 0)
-                b[slot] += A.a[k];
-            else
-                unsafeAtomicAdd(grad + old[k], A.a[k]);
+    const int dx = ix - A.ix, dy = iy - A.iy;
+    if (A.ix < 0 || dx < -1 || dx > 1 || dy < -1 || dy > 1) {
+        acc_flush(nx, A, E);  // nothing on an empty accumulator
+    } else {
+        int n0 = A.iy * nx + A.ix;
+        if (dx == 1) {  // leaves column ix_old behind
+            E.n[0] = n0;
+            E.v[0] = A.a[0];
+            E.n[1] = n0 + nx;
+            E.v[1] = A.a[2];
+            E.mask |= 3u;
+            A.a[0] = A.a[1];
+            A.a[2] = A.a[3];
+            A.a[1] = A.a[3] = (R)0;
+        } else if (dx == -1) {  // leaves column ix_old + 1 behind
+            E.n[0] = n0 + 1;
+            E.v[0] = A.a[1];
+            E.n[1] = n0 + nx + 1;
+            E.v[1] = A.a[3];
+            E.mask |= 3u;
+            A.a[1] = A.a[0];
+            A.a[3] = A.a[2];
+            A.a[0] = A.a[2] = (R)0;
+        }
+        n0 = A.iy * nx + ix;  // the accumulator now holds cell (ix, iy_old)
+        if (dy == 1) {
+            E.n[2] = n0;
+            E.v[2] = A.a[0];
+            E.n[3] = n0 + 1;
+            E.v[3] = A.a[1];
+            E.mask |= 0xcu;
+            A.a[0] = A.a[2];
+            A.a[1] = A.a[3];
+            A.a[2] = A.a[3] = (R)0;
+        } else if (dy == -1) {
+            E.n[2] = n0 + nx;
+            E.v[2] = A.a[2];
+            E.n[3] = n0 + nx + 1;
+            E.v[3] = A.a[3];
+            E.mask |= 0xcu;
+            A.a[2] = A.a[0];
+            A.a[3] = A.a[1];
+            A.a[0] = A.a[1] = (R)0;
         }
     }
-    A.n0 = n0;
-    for (int k = 0; k < 4; k++) A.a[k] = b[k];
+    A.ix = ix;
+    A.iy = iy;
 }
 
 template <class R>
-__device__ __forceinline__ void acc_add(R *grad, int nx, CellAcc<R> &A, const Sample<R> &s, R a)
+__device__ __forceinline__ void acc_add(int nx, CellAcc<R> &A, const Sample<R> &s, R a, Emit<R> &E)
 {
-    int64_t n0 = (int64_t)s.iy * nx + s.ix;
-    if (n0 != A.n0) acc_move(grad, nx, A, n0);
+    E.mask = 0;
+    if (s.ix != A.ix || s.iy != A.iy) acc_move(nx, A, s.ix, s.iy, E);
     R omt = (R)1 - s.t, oms = (R)1 - s.s;
     A.a[0] = fma(a * omt, oms, A.a[0]);
     A.a[1] = fma(a * s.t, oms, A.a[1]);
@@ -983,27 +1104,146 @@ __device__ __forceinline__ void acc_add(R *grad, int nx, CellAcc<R> &A, const Sa
     A.a[3] = fma(a * s.t, s.s, A.a[3]);
 }
 
-template <class R, bool COMP, int INTEG, bool BATCH>
-__global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs A, R *grad, BatchArgs B)
+// Node updates travel from the marching lanes of a block to its last wave
+// through one ring per lane in LDS; that wave alone issues the global float
+// atomics.  (Vector memory operations of a wave complete in issue order, so
+// atomics issued by a marching wave would hold up its next table loads.)  A
+// ring has one writer, its lane, which stores entries and then publishes its
+// head, and one reader, a lane of the last wave, which reads up to the head and
+// then publishes its tail.  LDS operations of a wave take effect in program
+// order, and compiler barriers keep that order in the code, so an entry is
+// stored before its head is visible and read before its slot is reused.  Every
+// wait is bounded: a bound that is hit sets the error word and the wait gives up.
+constexpr int kFlushLanes = 64;
+constexpr unsigned kQDone = 0x80000000u;
+constexpr unsigned kQSpin = 1u << 26;
+
+template <class R>
+struct QEntry {
+    unsigned node;  // node index; batches add the instance in the top 8 bits
+    R val;
+};
+
+template <class R>
+struct QRing {
+    static constexpr int kLen = 16;  // entries per marching lane (32 / 64 KB per block)
+};
+
+__device__ __forceinline__ void compiler_fence() { __asm__ volatile("" ::: "memory"); }
+
+template <class R>
+__device__ __forceinline__ void q_push(QEntry<R> *ring, unsigned *qhead, unsigned *qtail, int lane, int nm,
+                                       unsigned &head, unsigned &tailc, const Emit<R> &E, unsigned inst,
+                                       unsigned *err)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t n_items = BATCH ? B.off[B.n_inst] : A.n_pairs;
+    if (!E.mask) return;
+    const unsigned k = __popc(E.mask);
+    constexpr unsigned len = QRing<R>::kLen;
+    if (head + k - tailc > len) {
+        for (unsigned spins = 0;; spins++) {
+            tailc = __hip_atomic_load(qtail + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (head + k - tailc <= len) break;
+            if (spins > kQSpin) {
+                atomicOr(err, 1u);
+                return;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        compiler_fence();
+    }
+    for (int j = 0; j < 4; j++)
+        if (E.mask & (1u << j)) {
+            QEntry<R> &q = ring[(head & (len - 1)) * nm + lane];
+            q.node = (unsigned)E.n[j] | inst;
+            q.val = E.v[j];
+            head++;
+        }
+    compiler_fence();
+    __hip_atomic_store(qhead + lane, head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// The last wave of a block drains the rings of marching lanes lane, lane + 64,
+// ... into the grid until every one of them is marked done and empty.
+template <class R, bool BATCH>
+__device__ __forceinline__ void q_drain(const QEntry<R> *ring, const unsigned *qhead, unsigned *qtail, int nm,
+                                        R *grad, const BatchArgs &B, unsigned *err)
+{
+    constexpr unsigned len = QRing<R>::kLen;
+    const int lane = threadIdx.x - nm;
+    unsigned tl[kBlock / 64] = {};
+    for (unsigned idle = 0;;) {
+        bool done = true, moved = false;
+        for (int j = 0; j < kBlock / 64; j++) {
+            if (j * 64 >= nm) break;
+            const int pl = lane + 64 * j;
+            const unsigned h = __hip_atomic_load(qhead + pl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            compiler_fence();
+            const unsigned hh = h & ~kQDone;
+            while (tl[j] != hh) {
+                const QEntry<R> q = ring[(tl[j] & (len - 1)) * nm + pl];
+                R *g = grad;
+                unsigned node = q.node;
+                if (BATCH) {
+                    g = ((const Inst<R> *)B.inst)[node >> 24].grad;
+                    node &= 0xffffffu;
+                }
+                unsafeAtomicAdd(g + node, q.val);
+                tl[j]++;
+                moved = true;
+            }
+            compiler_fence();
+            __hip_atomic_store(qtail + pl, tl[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            done = done && (h & kQDone);
+        }
+        if (__all(done)) break;
+        if (!__any(moved)) {
+            if (++idle > kQSpin) {
+                atomicOr(err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+}
+
+// Marching lanes are threads 0 .. nm-1 (nm = blockDim.x - 64); the last wave
+// drains their node updates into the grid.
+template <class R, bool COMP, int INTEG, bool BATCH>
+__global__ void __launch_bounds__(kBlock + kFlushLanes) k_adjoint(Medium<R> M, Geo g, AdjArgs A, R *grad,
+                                                                   BatchArgs B)
+{
+    __shared__ QEntry<R> q_ring[QRing<R>::kLen * kBlock];
+    __shared__ unsigned q_head[kBlock], q_tail[kBlock];
+    const int nm = (int)blockDim.x - kFlushLanes;
+    for (int i = threadIdx.x; i < nm; i += blockDim.x) q_head[i] = q_tail[i] = 0;
+    __syncthreads();
+    if ((int)threadIdx.x >= nm) {
+        q_drain<R, BATCH>(q_ring, q_head, q_tail, nm, grad, B, A.err);
+        block_sum2(0ull, 0ull, A.stats);
+        return;
+    }
+    const int lane = threadIdx.x;
+    unsigned qh = 0, qt = 0;
+    const int64_t stride = (int64_t)gridDim.x * nm;
+    int64_t p = (int64_t)blockIdx.x * nm + lane;
+    int64_t n_items = BATCH ? B.off[B.n_inst] : A.n_items;
     int64_t q = p;
     int k = 0;
     Medium<R> m = M;
     Geo gg = g;
     AdjArgs a = A;
-    R *gr = grad;
     R ds = (R)gg.ds, R2 = (R)(gg.R * gg.R), cx = (R)gg.cx, cy = (R)gg.cy;
     unsigned long long n_steps = 0, n_rays = 0;
     Ray<R> ray;
     Slot<R> C[3];
     CellAcc<R> acc;
-    acc.n0 = -1;
+    acc.ix = acc.iy = -1;
     acc.a[0] = acc.a[1] = acc.a[2] = acc.a[3] = (R)0;
+    Emit<R> E;
+    E.mask = 0;
     R scale = 0;  // rho h
     bool active = false;
+    auto push = [&]() { q_push(q_ring, q_head, q_tail, lane, nm, qh, qt, E, BATCH ? (unsigned)k << 24 : 0u, A.err); };
 
     auto next_pair = [&]() {
         while (p < n_items) {
@@ -1013,23 +1253,18 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
                 m = I.M;
                 gg = I.g;
                 a = I.J;
-                gr = I.grad;
                 q = p - B.off[k];
                 ds = (R)gg.ds;
                 R2 = (R)(gg.R * gg.R);
                 cx = (R)gg.cx;
                 cy = (R)gg.cy;
-            } else {
-                q = p;
             }
             int e, r;
-            TraceArgs pa;
-            pa.pairs = a.pairs;
-            bool ok = pair_of(pa, gg, q, e, r);
+            bool ok = BATCH ? pair_of(TraceArgs{a.pairs}, gg, q, e, r) : adj_item(a, gg, p, e, r, q);
             ok = ok && (a.status[q] == RTX_RAY_LINKED || a.status[q] == RTX_RAY_NOT_CONVERGED);
             double rho = ok ? a.rho[q] : 0.0;
             if (ok && rho != 0.0) {
-                start_ray<R, COMP>(ray, gg, e, a.theta[q]);
+                start_ray<R, COMP>(ray, gg, emitter_of(gg, e), a.theta[q]);
                 slots_prime(m, C, ray, ds, INTEG);
                 scale = (R)(rho * gg.h);
                 active = true;
@@ -1053,7 +1288,8 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
         const bool exhausted = !bad && !crossed && (ray.m + 1 >= a.max_steps);
         if (!(bad || crossed || exhausted)) {
             const R w = ray.m == 0 ? ds * (R)0.5 : ds;
-            acc_add(gr, m.nx, acc, so.s1, scale * w * kap);
+            acc_add(m.nx, acc, so.s1, scale * w * kap, E);
+            push();
             nxt.m = ray.m + 1;
             ray = nxt;
             continue;
@@ -1065,17 +1301,23 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(Medium<R> M, Geo g, AdjArgs 
             Sample<R> sq = lookup_at<R, COMP>(m, gg, hit.qx, hit.qy);
             if (sq.c > (R)0) {
                 R wm = (R)(ray.m == 0 ? 0.5 * dsp : 0.5 * (gg.ds + dsp));
-                acc_add(gr, m.nx, acc, so.s1, scale * wm * kap);
+                acc_add(m.nx, acc, so.s1, scale * wm * kap, E);
+                push();
                 R icq = rcp(sq.c);
                 R kq = a.weight == RTX_W_DTDC ? -icq * icq : (R)1;
-                acc_add(gr, m.nx, acc, sq, scale * (R)(0.5 * dsp) * kq);
+                acc_add(m.nx, acc, sq, scale * (R)(0.5 * dsp) * kq, E);
+                push();
             }
         }
-        acc_flush(gr, m.nx, acc);
+        E.mask = 0;
+        acc_flush(m.nx, acc, E);
+        push();
         if (BATCH) mark_done(B, k);
         p += stride;
         next_pair();
     }
+    compiler_fence();
+    __hip_atomic_store(q_head + lane, qh | kQDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     block_sum2(n_steps, n_rays, A.stats);
 }
 
@@ -1282,7 +1524,7 @@ __global__ void __launch_bounds__(kBlock) k_weights(Medium<R> M, Geo g, WArgs A)
             ok = ok && (A.status[p] == RTX_RAY_LINKED || A.status[p] == RTX_RAY_NOT_CONVERGED);
             begin_row();
             if (ok) {
-                start_ray<R, COMP>(ray, g, e, A.theta[p]);
+                start_ray<R, COMP>(ray, g, emitter_of(g, e), A.theta[p]);
                 slots_prime(M, C, ray, ds, INTEG);
                 active = true;
                 return;
@@ -1444,6 +1686,7 @@ struct rtx_plan_s {
     void *tab = nullptr;  // packed medium
     bool have_medium = false;
     unsigned long long *stats = nullptr;  // [3][kMaxBlocks][2]: trace, fan link pass, adjoint
+    unsigned int *err = nullptr;          // device error word of the adjoint's LDS queue
     int stat_blocks[3] = {0, 0, 0};
     double *rho = nullptr;     // [max_pairs] ray-Born reduction
     double *omega = nullptr;   // [n_freq_cap]
@@ -1475,6 +1718,7 @@ struct rtx_batch_s {
     unsigned int *remain = nullptr;          // [2][n_inst]
     unsigned long long *times = nullptr;     // [1 + 2 n_inst]: t0, fwd done, adjoint done
     unsigned long long *stats = nullptr;     // [2][kMaxBlocks][2]
+    unsigned int *err = nullptr;             // device error word of the adjoint's LDS queue
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1576,6 +1820,20 @@ int grid_blocks_for(int n_cu, int block, K kernel, int64_t n)
     return (int)std::max<int64_t>(1, std::min<int64_t>({want, cap, (int64_t)kMaxBlocks}));
 }
 
+// The adjoint's blocks carry one extra wave (the queue drain) besides the
+// `block` marching lanes.
+template <class K>
+int adjoint_blocks_for(int n_cu, int block, K kernel, int64_t n)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block + kFlushLanes, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int64_t want = (n + block - 1) / block;
+    int64_t cap = (int64_t)n_cu * per_cu;
+    return (int)std::max<int64_t>(1, std::min<int64_t>({want, cap, (int64_t)kMaxBlocks}));
+}
+
 template <class K>
 int grid_blocks(const rtx_plan_s *P, K kernel, int64_t n)
 {
@@ -1645,11 +1903,13 @@ int launch_adjoint(rtx_plan_s *P, const AdjArgs &A, R *grad, hipStream_t s)
     Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
     Geo g = make_geo(P);
     auto kern = P->opts.integ == RTX_RK4 ? k_adjoint<R, COMP, 4, false> : k_adjoint<R, COMP, 2, false>;
-    int blocks = grid_blocks(P, kern, A.n_pairs);
+    int blocks = adjoint_blocks_for(P->n_cu, P->block, kern, A.n_items);
     P->stat_blocks[2] = blocks;
     BatchArgs B{};
+    AdjArgs a = A;
+    a.err = P->err;
     if (int rc = time_mark(P, RTX_SLOT_ADJOINT, 0, s)) return rc;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(P->block), 0, s, M, g, A, grad, B);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(P->block + kFlushLanes), 0, s, M, g, a, grad, B);
     HIP_TRY(hipGetLastError());
     return time_mark(P, RTX_SLOT_ADJOINT, 1, s);
 }
@@ -1811,9 +2071,10 @@ int batch_enqueue(rtx_batch_s *Bt, hipStream_t s)
         J.stats = Bt->stats + 2 * kMaxBlocks;
         B.remain = Bt->remain + Bt->n_inst;
         B.t_done = Bt->times + 1 + Bt->n_inst;
+        J.err = Bt->err;
         auto ka = Bt->opts.integ == RTX_RK4 ? k_adjoint<R, COMP, 4, true> : k_adjoint<R, COMP, 2, true>;
-        int ablocks = grid_blocks_for(Bt->n_cu, Bt->block, ka, Bt->total_pairs);
-        hipLaunchKernelGGL(ka, dim3(ablocks), dim3(Bt->block), 0, s, M, g, J, (R *)nullptr, B);
+        int ablocks = adjoint_blocks_for(Bt->n_cu, Bt->block, ka, Bt->total_pairs);
+        hipLaunchKernelGGL(ka, dim3(ablocks), dim3(Bt->block + kFlushLanes), 0, s, M, g, J, (R *)nullptr, B);
         HIP_TRY(hipGetLastError());
     }
     return RTX_OK;
@@ -1886,9 +2147,14 @@ int rtx_plan_create(rtx_plan *out, const rtx_grid *grid, const rtx_ring *ring, c
     P->n_cu = prop.multiProcessorCount;
     if (hipMalloc(&P->tab, tab_bytes) != hipSuccess ||
         hipMalloc((void **)&P->stats, sizeof(unsigned long long) * 3 * 2 * kMaxBlocks) != hipSuccess ||
+        hipMalloc((void **)&P->err, sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void **)&P->rho, sizeof(double) * max_pairs) != hipSuccess) {
         rtx_plan_destroy(P);
         return fail(RTX_E_NOMEM, "device allocation of the plan workspace failed");
+    }
+    if (hipMemset(P->err, 0, sizeof(unsigned int)) != hipSuccess) {
+        rtx_plan_destroy(P);
+        return fail(RTX_E_HIP, "clearing the plan's error word failed");
     }
     *out = P;
     return RTX_OK;
@@ -1900,6 +2166,7 @@ int rtx_plan_destroy(rtx_plan P)
     (void)hipDeviceSynchronize();
     if (P->tab) (void)hipFree(P->tab);
     if (P->stats) (void)hipFree(P->stats);
+    if (P->err) (void)hipFree(P->err);
     for (void *q : {(void *)P->f_g, (void *)P->f_T, (void *)P->f_L, (void *)P->f_st, P->f_seed})
         if (q) (void)hipFree(q);
     for (int k = 0; k < RTX_NUM_SLOTS; k++)
@@ -2042,6 +2309,15 @@ int rtx_tof_adjoint(rtx_plan P, const double *c, const int32_t *pairs, int64_t n
     A.weight = weight;
     A.max_steps = max_steps_of(P);
     A.stats = P->stats + 2 * 2 * kMaxBlocks;
+    A.err = P->err;
+    A.tile = 0;
+    A.n_items = n_pairs;
+    if (!pairs) {  // all ordered pairs: walk 16 x 16 element-cluster tiles
+        const int n = P->ring.n_elem;
+        A.tile = std::min(16, n);
+        const int64_t nc = (n + A.tile - 1) / A.tile;
+        A.n_items = nc * nc * A.tile * A.tile;
+    }
     if (P->opts.prec == RTX_F32C) return launch_adjoint<float, true>(P, A, (float *)grad, s);
     return launch_adjoint<double, false>(P, A, (double *)grad, s);
 }
@@ -2063,6 +2339,9 @@ int rtx_plan_stats(rtx_plan P, int64_t *trace_steps, int64_t *trace_rays, int64_
     if (trace_steps) *trace_steps = (int64_t)ts;
     if (trace_rays) *trace_rays = (int64_t)tr;
     if (adjoint_steps) *adjoint_steps = (int64_t)as;
+    unsigned int e = 0;
+    HIP_TRY(hipMemcpy(&e, P->err, sizeof e, hipMemcpyDeviceToHost));
+    if (e) return fail(RTX_E_HIP, "an adjoint's node-update queue hit its wait bound; its gradient is incomplete");
     return RTX_OK;
 }
 
@@ -2129,6 +2408,7 @@ int rtx_batch_create(rtx_batch *out, const rtx_opts *opts, int32_t weight, int32
     if (!out) return fail(RTX_E_ARG, "out is NULL");
     *out = nullptr;
     if (!opts || !inst || n_inst < 1) return fail(RTX_E_ARG, "need opts and at least one instance");
+    if (n_inst > 255) return fail(RTX_E_UNSUPPORTED, "a batch holds at most 255 instances (got %d)", n_inst);
     if (weight != RTX_W_LENGTH && weight != RTX_W_DTDC) return fail(RTX_E_ARG, "unknown weight %d", weight);
     if (rays_per_block == 0) rays_per_block = kBlock;
     if (rays_per_block != 64 && rays_per_block != 128 && rays_per_block != 256)
@@ -2142,8 +2422,8 @@ int rtx_batch_create(rtx_batch *out, const rtx_opts *opts, int32_t weight, int32
         int64_t all = (int64_t)I.ring.n_elem * (I.ring.n_elem - 1);
         if (I.n_pairs < 1 || (!I.pairs && I.n_pairs != all))
             return fail(RTX_E_ARG, "instance %d: bad n_pairs %lld", k, (long long)I.n_pairs);
-        if ((int64_t)(I.grid.nx - 1) * (I.grid.ny - 1) >= (1 << 24))
-            return fail(RTX_E_ARG, "instance %d: grid exceeds 2^24 cells", k);
+        if ((int64_t)I.grid.nx * I.grid.ny > (1 << 24))
+            return fail(RTX_E_ARG, "instance %d: a batch instance's grid holds at most 2^24 nodes", k);
         if (I.resid && !I.grad) return fail(RTX_E_ARG, "instance %d: resid needs grad", k);
         n_with_resid += I.resid != nullptr;
     }
@@ -2177,12 +2457,14 @@ int rtx_batch_create(rtx_batch *out, const rtx_opts *opts, int32_t weight, int32
         hipMalloc((void **)&Bt->off, sizeof(int64_t) * (n_inst + 1)) != hipSuccess ||
         hipMalloc((void **)&Bt->remain, sizeof(unsigned int) * 2 * n_inst) != hipSuccess ||
         hipMalloc((void **)&Bt->times, sizeof(unsigned long long) * (1 + 2 * n_inst)) != hipSuccess ||
-        hipMalloc((void **)&Bt->stats, sizeof(unsigned long long) * 4 * kMaxBlocks) != hipSuccess) {
+        hipMalloc((void **)&Bt->stats, sizeof(unsigned long long) * 4 * kMaxBlocks) != hipSuccess ||
+        hipMalloc((void **)&Bt->err, sizeof(unsigned int)) != hipSuccess) {
         rtx_batch_destroy(Bt);
         return fail(RTX_E_NOMEM, "batch workspace");
     }
     int rc = RTX_OK;
-    if (hipMemcpy(Bt->off, off.data(), sizeof(int64_t) * (n_inst + 1), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemset(Bt->err, 0, sizeof(unsigned int)) != hipSuccess) rc = fail(RTX_E_HIP, "clearing the error word failed");
+    if (!rc && hipMemcpy(Bt->off, off.data(), sizeof(int64_t) * (n_inst + 1), hipMemcpyHostToDevice) != hipSuccess)
         rc = fail(RTX_E_HIP, "upload of instance offsets failed");
     if (!rc) rc = opts->prec == RTX_F32C ? batch_upload<float>(Bt) : batch_upload<double>(Bt);
     if (rc) {
@@ -2224,6 +2506,9 @@ int rtx_batch_times(rtx_batch Bt, double *fwd_ms, double *done_ms)
     HIP_TRY(hipDeviceSynchronize());
     std::vector<unsigned long long> t(1 + 2 * Bt->n_inst);
     HIP_TRY(hipMemcpy(t.data(), Bt->times, sizeof(unsigned long long) * t.size(), hipMemcpyDeviceToHost));
+    unsigned int e = 0;
+    HIP_TRY(hipMemcpy(&e, Bt->err, sizeof e, hipMemcpyDeviceToHost));
+    if (e) return fail(RTX_E_HIP, "an adjoint's node-update queue hit its wait bound; its gradients are incomplete");
     int dev = 0, khz = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
@@ -2244,7 +2529,7 @@ int rtx_batch_destroy(rtx_batch Bt)
     if (Bt->graph) (void)hipGraphDestroy(Bt->graph);
     if (Bt->cap_stream) (void)hipStreamDestroy(Bt->cap_stream);
     for (void *q : {(void *)Bt->tabs, Bt->dinst, (void *)Bt->off, (void *)Bt->remain, (void *)Bt->times,
-                    (void *)Bt->stats})
+                    (void *)Bt->stats, (void *)Bt->err})
         if (q) (void)hipFree(q);
     delete Bt;
     return RTX_OK;

@@ -63,3 +63,20 @@ def test_no_cpu_fallback_in_product_path():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "oracle_rt" not in text, f
+
+
+def test_batch_limits_are_checked_on_the_host(lib):
+    """rtx_batch_create rejects more than 255 instances (the adjoint tags node
+    updates with an 8-bit instance index) before it touches a device."""
+    from paper_2511_18511_amd import _binding as B
+
+    opts = B.rtx_opts(B.RTX_F32C, B.RTX_RK4, 0.25, 1e-3, 30, 0, 0)
+    inst = (B.rtx_instance * 256)()
+    out = C.c_void_p()
+    lib.rtx_batch_create.restype = C.c_int
+    lib.rtx_last_error.restype = C.c_char_p
+    rc = lib.rtx_batch_create(C.byref(out), C.byref(opts), B.RTX_W_LENGTH, 0, 256, inst)
+    assert rc == B.RTX_E_UNSUPPORTED, rc
+    assert b"255" in lib.rtx_last_error()
+    rc = lib.rtx_batch_create(C.byref(out), C.byref(opts), 7, 0, 1, inst)  # unknown weight
+    assert rc == B.RTX_E_ARG
