@@ -76,12 +76,19 @@ enum rtx_integrator { RTX_HEUN = 2, RTX_RK4 = 4 };
 enum rtx_flags {
     RTX_WARM_START = 1u,  /* start linking from the given theta */
     RTX_FIXED_ANGLE = 2u, /* trace once at the given theta, no linking */
-    RTX_FAN_START = 4u    /* cold start seeded from the emitter's fan of straight rays
+    RTX_FAN_START = 4u,   /* cold start seeded from the emitter's fan of straight rays
                              (all ordered pairs only, pairs == NULL): every pair's
                              straight ray is traced first (its first traced ray);
                              the nearest sign change of the misfit over rays of
                              neighbouring receivers of the same emitter seeds the
                              secant; the linking rules are unchanged */
+    RTX_INTERP_BSPLINE = 8u /* plan-wide (set at rtx_plan_create, fixed after):
+                               interpolate c and its gradient with the
+                               interpolating cubic B-spline of the node values
+                               (Sec. 3.3; mirror extension at the grid edges)
+                               instead of bilinearly.  Tracing and forward calls
+                               only: adjoint, path weights and batches return
+                               RTX_E_UNSUPPORTED on such a plan */
 };
 enum rtx_weight { RTX_W_LENGTH = 0, RTX_W_DTDC = 1 };
 enum rtx_resid_kind { RTX_RESID_REAL = 0, RTX_RESID_RAYBORN_C64 = 1 };

@@ -18,6 +18,7 @@ from ._binding import (  # noqa: F401
 
 PRECISIONS = {"f64": B.RTX_F64, "f32c": B.RTX_F32C}
 INTEGRATORS = {"heun": B.RTX_HEUN, "rk4": B.RTX_RK4}
+INTERPOLATIONS = {"bilinear": 0, "bspline": B.RTX_INTERP_BSPLINE}
 
 
 def _ptr(t):
@@ -38,13 +39,17 @@ def _dev_check(t, dtype, shape=None, name="tensor"):
 class Plan:
     """Geometry + options + device workspace (the packed medium).
 
-    Lengths are metres; ``ds_px``/``tol_px`` are in grid pixels."""
+    Lengths are metres; ``ds_px``/``tol_px`` are in grid pixels.  ``interp``
+    is "bilinear" (all calls) or "bspline" (the cubic B-spline of Sec. 3.3:
+    tracing only, no adjoint or path weights)."""
 
     def __init__(self, nx, ny, h, n_elem, radius, phi0=0.0, prec="f32c", integ="rk4", ds_px=0.25, tol_px=1e-3,
-                 max_marches=30, max_steps=0, max_pairs=None):
+                 max_marches=30, max_steps=0, max_pairs=None, interp="bilinear"):
         self.nx, self.ny, self.h = int(nx), int(ny), float(h)
         self.n_elem, self.radius, self.phi0 = int(n_elem), float(radius), float(phi0)
         self.prec = prec
+        self.interp = interp
+        self._interp_flag = INTERPOLATIONS[interp]
         self.real = torch.float32 if prec == "f32c" else torch.float64
         self.n_all = self.n_elem * (self.n_elem - 1)
         self.max_pairs = int(max_pairs or self.n_all)
@@ -56,7 +61,7 @@ class Plan:
     def _make_opts(self, flags, **over):
         o = dict(self._opts, **over)
         return B.rtx_opts(PRECISIONS[self.prec], INTEGRATORS[o["integ"]], float(o["ds_px"]), float(o["tol_px"]),
-                          int(o["max_marches"]), int(o["max_steps"]), int(flags))
+                          int(o["max_marches"]), int(o["max_steps"]), int(flags) | self._interp_flag)
 
     def _apply(self, flags, **over):
         B.rtx_plan_set_opts(self._handle, self._make_opts(flags, **over))

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_HERE, "librtx.so")
 RTX_OK, RTX_E_ARG, RTX_E_HIP, RTX_E_NOMEM, RTX_E_UNSUPPORTED, RTX_E_CAPACITY = 0, -1, -2, -3, -4, -5
 RTX_F64, RTX_F32C = 0, 1
 RTX_HEUN, RTX_RK4 = 2, 4
-RTX_WARM_START, RTX_FIXED_ANGLE, RTX_FAN_START = 1, 2, 4
+RTX_WARM_START, RTX_FIXED_ANGLE, RTX_FAN_START, RTX_INTERP_BSPLINE = 1, 2, 4, 8
 RTX_SLOT_PACK, RTX_SLOT_TRACE, RTX_SLOT_FAN_SEED, RTX_SLOT_FAN_LINK, RTX_SLOT_ADJOINT, RTX_NUM_SLOTS = 0, 1, 2, 3, 4, 5
 RTX_W_LENGTH, RTX_W_DTDC = 0, 1
 RTX_RESID_REAL, RTX_RESID_RAYBORN_C64 = 0, 1

@@ -107,6 +107,77 @@ __global__ void k_pack(const double *__restrict__ c, int nx, int ny, R *__restri
     }
 }
 
+// ------------------------------------------------------- cubic B-spline --
+// Sec. 3.3's cubic B-spline option: the field is the interpolating cubic
+// B-spline of the node values, sum_k q_k B(u - k) with the centred cubic
+// B-spline B, and the coefficients q solve sum_k B(j - k) q_k = c_j, the
+// signal extended by mirroring about the first and last nodes.  Along each
+// line the solve is the standard pair of first-order recursions with pole
+// z = sqrt(3) - 2: a causal pass seeded with the sum of z^k over the mirrored
+// signal (period 2(n - 1)), an anti-causal pass seeded from the mirror
+// condition, and a gain of 6.  Rows first, then columns; FP64 throughout.
+__device__ void bsp_filter(double *v, int n, int stride)
+{
+    const double z = 1.7320508075688772 - 2.0;
+    const int period = 2 * (n - 1);
+    double zk = 1.0, sum = 0.0;
+    for (int k = 0; k < period && zk != 0.0; k++) {  // z^k underflows long before k = period on large grids
+        const int j = k < n ? k : period - k;
+        sum += zk * v[(size_t)j * stride];
+        zk *= z;
+    }
+    double zp = 1.0;  // z^period
+    for (int k = 0; k < period && zp != 0.0; k++) zp *= z;
+    double prev = sum / (1.0 - zp);
+    v[0] = prev;
+    for (int k = 1; k < n; k++) {
+        prev = v[(size_t)k * stride] + z * prev;
+        v[(size_t)k * stride] = prev;
+    }
+    double nxt = (z / (z * z - 1.0)) * (v[(size_t)(n - 1) * stride] + z * v[(size_t)(n - 2) * stride]);
+    v[(size_t)(n - 1) * stride] = nxt;
+    for (int k = n - 2; k >= 0; k--) {
+        nxt = z * (nxt - v[(size_t)k * stride]);
+        v[(size_t)k * stride] = nxt;
+    }
+    for (int k = 0; k < n; k++) v[(size_t)k * stride] *= 6.0;
+}
+
+// One thread per row (rows = true) or column of the coefficient grid.
+__global__ void k_bsp_lines(const double *__restrict__ c, double *__restrict__ q, int nx, int ny, bool rows)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (rows) {
+        if (i >= ny) return;
+        for (int k = 0; k < nx; k++) q[(size_t)i * nx + k] = c[(size_t)i * nx + k];
+        bsp_filter(q + (size_t)i * nx, nx, 1);
+    } else {
+        if (i >= nx) return;
+        bsp_filter(q + i, ny, nx);
+    }
+}
+
+__device__ __forceinline__ int mirror_index(int i, int n)
+{
+    return i < 0 ? -i : i > n - 1 ? 2 * (n - 1) - i : i;
+}
+
+// One thread per cell: the 4 x 4 coefficients q[iy-1+b][ix-1+a] (b, a = 0..3),
+// row by row, mirrored at the grid edges.
+template <class R>
+__global__ void k_pack_bsp(const double *__restrict__ q, int nx, int ny, R *__restrict__ tab)
+{
+    const int ncx = nx - 1;
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= (int64_t)ncx * (ny - 1)) return;
+    const int ix = (int)(cell % ncx), iy = (int)(cell / ncx);
+    R *o = tab + cell * 16;
+    for (int b = 0; b < 4; b++) {
+        const int jy = mirror_index(iy - 1 + b, ny);
+        for (int a = 0; a < 4; a++) o[4 * b + a] = (R)q[(size_t)jy * nx + mirror_index(ix - 1 + a, nx)];
+    }
+}
+
 // -------------------------------------------------------------- arithmetic --
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // FP64: hardware reciprocal refined by two Newton steps (within an ulp of 1/x;
@@ -207,6 +278,71 @@ __device__ __forceinline__ Sample<R> lookup(const Medium<R> &M, R uh, R du, R vh
     o.c = fma(o.s, fma(o.t, v[3], v[2]), fma(o.t, v[1], v[0]));
     o.gx = fma(o.s, fma(o.t, v[7], v[6]), fma(o.t, v[5], v[4]));
     o.gy = fma(o.s, fma(o.t, v[11], v[10]), fma(o.t, v[9], v[8]));
+    return o;
+}
+
+// Cubic B-spline sample at (uh + du, vh + dv): same cell and local
+// coordinates as `lookup`; weights of the stencil offsets -1..2 and their
+// derivatives, contracted over x, then y.  (16 coefficients per cell: 64 B in
+// FP32, four 16-byte loads.)
+template <class R>
+__device__ __forceinline__ void bsp_weights(R t, R (&w)[4], R (&dw)[4])
+{
+    const R u = (R)1 - t, t2 = t * t;
+    w[0] = u * u * u * (R)(1.0 / 6.0);
+    w[1] = fma(t2, fma(t, (R)0.5, (R)-1), (R)(2.0 / 3.0));
+    w[2] = fma(t, fma(t, fma(t, (R)-0.5, (R)0.5), (R)0.5), (R)(1.0 / 6.0));
+    w[3] = t2 * t * (R)(1.0 / 6.0);
+    dw[0] = (R)-0.5 * u * u;
+    dw[1] = t * fma(t, (R)1.5, (R)-2);
+    dw[2] = fma(t, fma(t, (R)-1.5, (R)1), (R)0.5);
+    dw[3] = (R)0.5 * t2;
+}
+
+__device__ __forceinline__ void load_stencil(const float *tab, uint32_t cell, float (&v)[16])
+{
+    const GLOBAL_AS float4 *p = (const GLOBAL_AS float4 *)((const GLOBAL_AS char *)tab + cell * 64u);
+    for (int k = 0; k < 4; k++) {
+        float4 a = p[k];
+        v[4 * k] = a.x, v[4 * k + 1] = a.y, v[4 * k + 2] = a.z, v[4 * k + 3] = a.w;
+    }
+}
+
+__device__ __forceinline__ void load_stencil(const double *tab, uint32_t cell, double (&v)[16])
+{
+    const GLOBAL_AS double2 *p = (const GLOBAL_AS double2 *)((const GLOBAL_AS char *)tab + (size_t)cell * 128u);
+    for (int k = 0; k < 8; k++) {
+        double2 a = p[k];
+        v[2 * k] = a.x, v[2 * k + 1] = a.y;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ Sample<R> lookup_bsp(const Medium<R> &M, R uh, R du, R vh, R dv)
+{
+    Sample<R> o;
+    o.ix = min(max((int)(uh + du), 0), M.nx - 2);
+    o.iy = min(max((int)(vh + dv), 0), M.ny - 2);
+    o.t = fmin_(fmax_((uh - (R)o.ix) + du, (R)0), (R)1);
+    o.s = fmin_(fmax_((vh - (R)o.iy) + dv, (R)0), (R)1);
+    R q[16], wx[4], dwx[4], wy[4], dwy[4];
+    load_stencil(M.tab, __umul24((uint32_t)o.iy, (uint32_t)(M.nx - 1)) + (uint32_t)o.ix, q);
+    bsp_weights(o.t, wx, dwx);
+    bsp_weights(o.s, wy, dwy);
+    R c = 0, gx = 0, gy = 0;
+    for (int b = 0; b < 4; b++) {
+        R r = 0, rx = 0;
+        for (int a = 0; a < 4; a++) {
+            r = fma(q[4 * b + a], wx[a], r);
+            rx = fma(q[4 * b + a], dwx[a], rx);
+        }
+        c = fma(r, wy[b], c);
+        gx = fma(rx, wy[b], gx);
+        gy = fma(r, dwy[b], gy);
+    }
+    o.c = c;
+    o.gx = gx;
+    o.gy = gy;
     return o;
 }
 
@@ -432,6 +568,15 @@ struct SlotSampler {
     }
 };
 
+// Cubic B-spline lookups (no slots: a 16-coefficient stencil per sample).
+template <class R>
+struct BspSampler {
+    const Medium<R> &M;
+    R uh, vh;
+    __device__ __forceinline__ Sample<R> get(int, R du, R dv) { return lookup_bsp(M, uh, du, vh, dv); }
+    __device__ __forceinline__ void done(int) {}
+};
+
 // Direct lookups: the recovery path of a step with a point outside its slot.
 template <class R>
 struct LookupSampler {
@@ -441,16 +586,21 @@ struct LookupSampler {
     __device__ __forceinline__ void done(int) {}
 };
 
-template <class R, bool COMP, int INTEG>
+template <class R, bool COMP, int INTEG, bool BSP = false>
 __device__ __forceinline__ StepOut<R> ray_step(const Medium<R> &M, Slot<R> (&C)[3], const Ray<R> &y, Ray<R> &nxt,
                                                R ds)
 {
     StageOut<R> st;
-    SlotSampler<R, INTEG> fs{M, C, y.uh, y.ul, y.vh, y.vl, y.dxh + y.dxl, y.dyh + y.dyl, y.kx, y.ky, ds, (R)0};
-    stages<R, INTEG>(fs, y, ds, st);
-    if (!(fs.dev < (R)0.5)) {
-        LookupSampler<R> ls{M, y.uh, y.vh};
-        stages<R, INTEG>(ls, y, ds, st);
+    if (BSP) {
+        BspSampler<R> bs{M, y.uh, y.vh};
+        stages<R, INTEG>(bs, y, ds, st);
+    } else {
+        SlotSampler<R, INTEG> fs{M, C, y.uh, y.ul, y.vh, y.vl, y.dxh + y.dxl, y.dyh + y.dyl, y.kx, y.ky, ds, (R)0};
+        stages<R, INTEG>(fs, y, ds, st);
+        if (!(fs.dev < (R)0.5)) {
+            LookupSampler<R> ls{M, y.uh, y.vh};
+            stages<R, INTEG>(ls, y, ds, st);
+        }
     }
     StepOut<R> o;
     o.s1 = st.s1;
@@ -560,13 +710,13 @@ __device__ __forceinline__ Hit intersect(const Geo &g, const Ray<R> &a, const Ra
 }
 
 // Medium at a ring-centred FP64 pixel point.
-template <class R, bool COMP>
+template <class R, bool COMP, bool BSP = false>
 __device__ __forceinline__ Sample<R> lookup_at(const Medium<R> &M, const Geo &g, double px, double py)
 {
     double u = px + g.cx, v = py + g.cy;
     R uh = (R)u, vh = (R)v;
     R ul = COMP ? (R)(u - (double)uh) : (R)0, vl = COMP ? (R)(v - (double)vh) : (R)0;
-    return lookup(M, uh, ul, vh, vl);
+    return BSP ? lookup_bsp(M, uh, ul, vh, vl) : lookup(M, uh, ul, vh, vl);
 }
 
 // ------------------------------------------------------------------ linking --
@@ -811,7 +961,7 @@ __device__ __forceinline__ void mark_done(const BatchArgs &B, int k)
     if (atomicSub(B.remain + k, 1u) == 1u) B.t_done[k] = wall_clock64();
 }
 
-template <class R, bool COMP, int INTEG, bool BATCH, bool FAN = false>
+template <class R, bool COMP, int INTEG, bool BATCH, bool FAN = false, bool BSP = false>
 __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs A, BatchArgs B)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -898,7 +1048,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
                     }
                 }
                 start_ray<R, COMP>(ray, gg, em, th);
-                slots_prime(m, C, ray, ds, INTEG);
+                if (!BSP) slots_prime(m, C, ray, ds, INTEG);
                 active = true;
                 return;
             }
@@ -913,7 +1063,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
 
     while (active) {
         Ray<R> nxt;
-        StepOut<R> so = ray_step<R, COMP, INTEG>(m, C, ray, nxt, ds);
+        StepOut<R> so = ray_step<R, COMP, INTEG, BSP>(m, C, ray, nxt, ds);
         n_steps++;
         const R w_start = ray.m == 0 ? ds * (R)0.5 : ds;
         const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
@@ -938,7 +1088,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
         } else if (crossed) {
             Hit hit = intersect<R>(gg, ray, nxt);
             double dsp = hit.t * gg.ds;
-            Sample<R> sq = lookup_at<R, COMP>(m, gg, hit.qx, hit.qy);
+            Sample<R> sq = lookup_at<R, COMP, BSP>(m, gg, hit.qx, hit.qy);
             if (!(sq.c > (R)0)) {
                 st = RTX_RAY_BAD_INPUT;
             } else {
@@ -988,7 +1138,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
             if (!pair_done) {
                 L.th = th_next;
                 start_ray<R, COMP>(ray, gg, em, th_next);
-                slots_prime(m, C, ray, ds, INTEG);
+                if (!BSP) slots_prime(m, C, ray, ds, INTEG);
             }
         }
         if (pair_done) {
@@ -1685,6 +1835,8 @@ struct rtx_plan_s {
     int64_t max_pairs;
     void *tab = nullptr;  // packed medium
     bool have_medium = false;
+    bool bsp = false;          // cubic B-spline interpolation (RTX_INTERP_BSPLINE)
+    double *bsp_q = nullptr;   // [ny][nx] B-spline coefficients (FP64)
     unsigned long long *stats = nullptr;  // [3][kMaxBlocks][2]: trace, fan link pass, adjoint
     unsigned int *err = nullptr;          // device error word of the adjoint's LDS queue
     int stat_blocks[3] = {0, 0, 0};
@@ -1796,7 +1948,16 @@ int pack(rtx_plan_s *P, const double *c, hipStream_t s)
     int64_t cells = (int64_t)(P->grid.nx - 1) * (P->grid.ny - 1);
     int blocks = (int)((cells + kBlock - 1) / kBlock);
     if (int rc = time_mark(P, RTX_SLOT_PACK, 0, s)) return rc;
-    if (P->opts.prec == RTX_F32C)
+    if (P->bsp) {
+        const int nx = P->grid.nx, ny = P->grid.ny;
+        hipLaunchKernelGGL(k_bsp_lines, dim3((ny + 63) / 64), dim3(64), 0, s, c, P->bsp_q, nx, ny, true);
+        hipLaunchKernelGGL(k_bsp_lines, dim3((nx + 63) / 64), dim3(64), 0, s, c, P->bsp_q, nx, ny, false);
+        if (P->opts.prec == RTX_F32C)
+            hipLaunchKernelGGL(k_pack_bsp<float>, dim3(blocks), dim3(kBlock), 0, s, P->bsp_q, nx, ny, (float *)P->tab);
+        else
+            hipLaunchKernelGGL(k_pack_bsp<double>, dim3(blocks), dim3(kBlock), 0, s, P->bsp_q, nx, ny,
+                               (double *)P->tab);
+    } else if (P->opts.prec == RTX_F32C)
         hipLaunchKernelGGL(k_pack<float>, dim3(blocks), dim3(kBlock), 0, s, c, P->grid.nx, P->grid.ny,
                            (float *)P->tab);
     else
@@ -1845,7 +2006,9 @@ int launch_trace(rtx_plan_s *P, const TraceArgs &A, hipStream_t s, int region = 
 {
     Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
     Geo g = make_geo(P);
-    auto kern = P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false, FAN> : k_trace<R, COMP, 2, false, FAN>;
+    auto kern = P->bsp ? (P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false, FAN, true>
+                                                   : k_trace<R, COMP, 2, false, FAN, true>)
+                       : (P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false, FAN> : k_trace<R, COMP, 2, false, FAN>);
     int blocks = grid_blocks(P, kern, A.n_pairs);
     P->stat_blocks[region] = blocks;
     BatchArgs B{};
@@ -2137,7 +2300,8 @@ int rtx_plan_create(rtx_plan *out, const rtx_grid *grid, const rtx_ring *ring, c
     P->opts = *opts;
     P->max_pairs = max_pairs;
     size_t esz = opts->prec == RTX_F32C ? sizeof(float) : sizeof(double);
-    size_t tab_bytes = (size_t)(grid->nx - 1) * (grid->ny - 1) * kCoef * esz;
+    P->bsp = (opts->flags & RTX_INTERP_BSPLINE) != 0;
+    size_t tab_bytes = (size_t)(grid->nx - 1) * (grid->ny - 1) * (P->bsp ? 16 : kCoef) * esz;
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -2148,7 +2312,8 @@ int rtx_plan_create(rtx_plan *out, const rtx_grid *grid, const rtx_ring *ring, c
     if (hipMalloc(&P->tab, tab_bytes) != hipSuccess ||
         hipMalloc((void **)&P->stats, sizeof(unsigned long long) * 3 * 2 * kMaxBlocks) != hipSuccess ||
         hipMalloc((void **)&P->err, sizeof(unsigned int)) != hipSuccess ||
-        hipMalloc((void **)&P->rho, sizeof(double) * max_pairs) != hipSuccess) {
+        hipMalloc((void **)&P->rho, sizeof(double) * max_pairs) != hipSuccess ||
+        (P->bsp && hipMalloc((void **)&P->bsp_q, sizeof(double) * grid->nx * grid->ny) != hipSuccess)) {
         rtx_plan_destroy(P);
         return fail(RTX_E_NOMEM, "device allocation of the plan workspace failed");
     }
@@ -2167,6 +2332,7 @@ int rtx_plan_destroy(rtx_plan P)
     if (P->tab) (void)hipFree(P->tab);
     if (P->stats) (void)hipFree(P->stats);
     if (P->err) (void)hipFree(P->err);
+    if (P->bsp_q) (void)hipFree(P->bsp_q);
     for (void *q : {(void *)P->f_g, (void *)P->f_T, (void *)P->f_L, (void *)P->f_st, P->f_seed})
         if (q) (void)hipFree(q);
     for (int k = 0; k < RTX_NUM_SLOTS; k++)
@@ -2182,6 +2348,8 @@ int rtx_plan_set_opts(rtx_plan P, const rtx_opts *opts)
     g_last_error.clear();
     if (!P || !opts) return fail(RTX_E_ARG, "null plan/opts");
     if (opts->prec != P->opts.prec) return fail(RTX_E_ARG, "precision of a plan cannot change");
+    if ((opts->flags ^ P->opts.flags) & RTX_INTERP_BSPLINE)
+        return fail(RTX_E_ARG, "the interpolation (RTX_INTERP_BSPLINE) of a plan cannot change");
     int rc = check_opts(&P->grid, &P->ring, opts);
     if (rc) return rc;
     P->opts = *opts;
@@ -2213,6 +2381,7 @@ int rtx_trace_rays(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_
     }
     if (!theta || !status) return fail(RTX_E_ARG, "theta and status are required");
     if (!w_rowptr && (w_col || w_val)) return fail(RTX_E_ARG, "w_col/w_val need w_rowptr");
+    if (w_rowptr && P->bsp) return fail(RTX_E_UNSUPPORTED, "path weights are bilinear-only (plan uses RTX_INTERP_BSPLINE)");
     if (w_col && nnz_cap < 0) return fail(RTX_E_ARG, "nnz_cap < 0");
     hipStream_t s = (hipStream_t)stream;
     rc = pack(P, c, s);
@@ -2266,6 +2435,7 @@ int rtx_tof_adjoint(rtx_plan P, const double *c, const int32_t *pairs, int64_t n
     int rc = check_pairs(P, pairs, n_pairs);
     if (rc) return rc;
     if (!grad) return fail(RTX_E_ARG, "grad is required");
+    if (P->bsp) return fail(RTX_E_UNSUPPORTED, "the adjoint is bilinear-only (plan uses RTX_INTERP_BSPLINE)");
     if (n_pairs == 0) return pack(P, c, (hipStream_t)stream);
     if (!theta || !status || !resid) return fail(RTX_E_ARG, "theta, status and resid are required");
     if (weight != RTX_W_LENGTH && weight != RTX_W_DTDC) return fail(RTX_E_ARG, "unknown weight %d", weight);
@@ -2409,6 +2579,7 @@ int rtx_batch_create(rtx_batch *out, const rtx_opts *opts, int32_t weight, int32
     *out = nullptr;
     if (!opts || !inst || n_inst < 1) return fail(RTX_E_ARG, "need opts and at least one instance");
     if (n_inst > 255) return fail(RTX_E_UNSUPPORTED, "a batch holds at most 255 instances (got %d)", n_inst);
+    if (opts->flags & RTX_INTERP_BSPLINE) return fail(RTX_E_UNSUPPORTED, "batches are bilinear-only");
     if (weight != RTX_W_LENGTH && weight != RTX_W_DTDC) return fail(RTX_E_ARG, "unknown weight %d", weight);
     if (rays_per_block == 0) rays_per_block = kBlock;
     if (rays_per_block != 64 && rays_per_block != 128 && rays_per_block != 256)

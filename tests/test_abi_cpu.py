@@ -80,3 +80,7 @@ def test_batch_limits_are_checked_on_the_host(lib):
     assert b"255" in lib.rtx_last_error()
     rc = lib.rtx_batch_create(C.byref(out), C.byref(opts), 7, 0, 1, inst)  # unknown weight
     assert rc == B.RTX_E_ARG
+    # the cubic B-spline medium is a tracing-only option: batches reject it
+    opts_b = B.rtx_opts(B.RTX_F32C, B.RTX_RK4, 0.25, 1e-3, 30, 0, B.RTX_INTERP_BSPLINE)
+    rc = lib.rtx_batch_create(C.byref(out), C.byref(opts_b), B.RTX_W_LENGTH, 0, 1, inst)
+    assert rc == B.RTX_E_UNSUPPORTED, rc
