@@ -121,20 +121,24 @@ typedef struct {
 } rtx_opts;
 
 /* Creates a plan: validates grid/ring/opts and allocates device workspace for
-   the packed medium (12 coefficients per grid cell in the plan's precision) and
-   for up to max_pairs pairs per call.  *out receives the plan (host object). */
+   the packed medium (12 coefficients per grid cell in the plan's precision; 16
+   with RTX_INTERP_BSPLINE, plus an FP64 [ny][nx] coefficient grid) and for up
+   to max_pairs pairs per call.  *out receives the plan (host object). */
 int rtx_plan_create(rtx_plan *out, const rtx_grid *grid, const rtx_ring *ring, const rtx_opts *opts,
                     int64_t max_pairs);
 
 /* Frees the plan's device memory (synchronises the device first). */
 int rtx_plan_destroy(rtx_plan plan);
 
-/* Changes the per-call options (precision must not change). */
+/* Changes the per-call options (precision and RTX_INTERP_BSPLINE must not
+   change: RTX_E_ARG). */
 int rtx_plan_set_opts(rtx_plan plan, const rtx_opts *opts);
 
 /* Packs the medium: c (device, float64 [ny][nx], m/s) -> node gradient and
-   per-cell bilinear coefficients of (c, dc/dx, dc/dy) in the plan's precision.
-   Later calls may pass c == NULL to reuse it. */
+   per-cell bilinear coefficients of (c, dc/dx, dc/dy) in the plan's precision
+   (Sec. 3.3); on an RTX_INTERP_BSPLINE plan, the interpolating cubic B-spline
+   coefficients (recursive prefilter in FP64, mirror extension) and each cell's
+   4 x 4 stencil of them.  Later calls may pass c == NULL to reuse it. */
 int rtx_set_medium(rtx_plan plan, const double *c, void *stream);
 
 /* Linked ray tracing of n_pairs pairs (Sec. 3.2, 3.4): for each pair
@@ -162,6 +166,22 @@ int rtx_trace_rays(rtx_plan plan, const double *c, const int32_t *pairs, int64_t
    same as rtx_trace_rays with len, miss, n_marches and weights omitted. */
 int rtx_tof_forward(rtx_plan plan, const double *c, const int32_t *pairs, int64_t n_pairs, double *theta,
                     double *tof, int8_t *status, void *stream);
+
+/* Free march without a ring: the ray equations of Sec. 3.2 followed for a
+   fixed number of steps, as in the trajectory (radius) experiment of Sec. 4.1.
+     x0   [n_rays][2] float64, device: start points, metres from the grid centre
+     d0   [n_rays][2] float64, device: start directions (normalised on the device)
+     pts  [n_rays][n_steps + 1][2] float64, device, caller-owned: the start
+          point and the end point of every step, metres from the grid centre
+   The plan's step ds_px, integrator, precision and interpolation apply; the
+   ring plays no part.  From the first point outside the node rectangle on (and
+   for a zero or non-finite direction) the points are NaN.  Near the edges the
+   stage points of a step sample the field of the nearest cell.
+   c: as in rtx_trace_rays.  Errors: n_rays < 0 or >= 2^31 - 256, n_steps < 0
+   or >= 2^30, missing buffers -> RTX_E_ARG (nothing enqueued); n_rays == 0
+   only packs c. */
+int rtx_march_free(rtx_plan plan, const double *c, int64_t n_rays, const double *x0, const double *d0,
+                   int32_t n_steps, double *pts, void *stream);
 
 /* Adjoint of the path weights along the rays traced at the given theta:
      grad_j += sum_i rho_i sum_m w_m h kappa_m phi_j(p_m)

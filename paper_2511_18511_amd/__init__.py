@@ -121,6 +121,21 @@ class Plan:
             out["w_rowptr"], out["w_col"], out["w_val"] = self.weights(out["theta"], pairs=pairs, **over)
         return out
 
+    def march(self, x0, d0, n_steps, c=None, **over):
+        """Free march without the ring: rays from x0 (float64 [n, 2] device,
+        metres from the grid centre) along d0 (float64 [n, 2], any length),
+        n_steps steps each.  Returns float64 [n, n_steps + 1, 2] positions in
+        metres (NaN once a ray has left the grid)."""
+        if c is not None:
+            _dev_check(c, torch.float64, (self.ny, self.nx), "c")
+        n = x0.shape[0]
+        _dev_check(x0, torch.float64, (n, 2), "x0")
+        _dev_check(d0, torch.float64, (n, 2), "d0")
+        pts = torch.empty(n, int(n_steps) + 1, 2, dtype=torch.float64, device=x0.device)
+        self._apply(0, **over)
+        B.rtx_march_free(self._handle, _ptr(c), n, _ptr(x0), _ptr(d0), int(n_steps), _ptr(pts), _stream())
+        return pts
+
     def weights(self, theta, pairs=None, **over):
         """System-matrix rows W_ij = h sum_m w_m phi_j(p_m) of the rays traced at
         the given angles, as CSR device tensors (rowptr int64 [n+1], col int32

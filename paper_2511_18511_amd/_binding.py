@@ -18,7 +18,7 @@ RTX_RAY_LINKED, RTX_RAY_NOT_CONVERGED, RTX_RAY_NO_HIT, RTX_RAY_BAD_INPUT = 0, 1,
 
 # every symbol include/rtx.h declares
 EXPORTS = ("rtx_plan_create", "rtx_plan_destroy", "rtx_plan_set_opts", "rtx_set_medium", "rtx_trace_rays",
-           "rtx_tof_forward", "rtx_tof_adjoint", "rtx_plan_stats", "rtx_plan_region_stats", "rtx_plan_timing",
+           "rtx_tof_forward", "rtx_march_free", "rtx_tof_adjoint", "rtx_plan_stats", "rtx_plan_region_stats", "rtx_plan_timing",
            "rtx_plan_timings", "rtx_plan_set_launch", "rtx_batch_create",
            "rtx_batch_run", "rtx_batch_times", "rtx_batch_destroy", "rtx_last_error")
 
@@ -68,6 +68,7 @@ def load():
     L.rtx_set_medium.argtypes = [vp, vp, vp]
     L.rtx_trace_rays.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
     L.rtx_tof_forward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+    L.rtx_march_free.argtypes = [vp, vp, i64, vp, vp, C.c_int32, vp, vp]
     L.rtx_tof_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(C.c_double), i32, i32, vp, vp]
     L.rtx_plan_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.rtx_plan_set_launch.argtypes = [vp, i32]
@@ -117,6 +118,10 @@ def rtx_trace_rays(plan, c, pairs, n_pairs, theta, tof, len_, miss_px, n_marches
 
 def rtx_tof_forward(plan, c, pairs, n_pairs, theta, tof, status, stream):
     return check(load().rtx_tof_forward(plan, c, pairs, int(n_pairs), theta, tof, status, stream))
+
+
+def rtx_march_free(plan, c, n_rays, x0, d0, n_steps, pts, stream):
+    return check(load().rtx_march_free(plan, c, int(n_rays), x0, d0, int(n_steps), pts, stream))
 
 
 def rtx_tof_adjoint(plan, c, pairs, n_pairs, theta, status, tof, resid, resid_kind, freqs_hz, n_freq, weight, grad,

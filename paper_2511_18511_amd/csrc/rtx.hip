@@ -410,11 +410,10 @@ struct Ray {
     int m;     // steps taken in this ray
 };
 
+// Ray at grid point (pu, pv) with unit direction (cp, sp).
 template <class R, bool COMP>
-__device__ __forceinline__ void ray_start(Ray<R> &ray, double pu, double pv, double psi)
+__device__ __forceinline__ void ray_set(Ray<R> &ray, double pu, double pv, double cp, double sp)
 {
-    double sp, cp;
-    sincos(psi, &sp, &cp);
     ray.uh = (R)pu;
     ray.vh = (R)pv;
     ray.dxh = (R)cp;
@@ -430,6 +429,14 @@ __device__ __forceinline__ void ray_start(Ray<R> &ray, double pu, double pv, dou
     ray.Th = ray.Tl = (R)0;
     ray.kx = ray.ky = (R)0;
     ray.m = 0;
+}
+
+template <class R, bool COMP>
+__device__ __forceinline__ void ray_start(Ray<R> &ray, double pu, double pv, double psi)
+{
+    double sp, cp;
+    sincos(psi, &sp, &cp);
+    ray_set<R, COMP>(ray, pu, pv, cp, sp);
 }
 
 // Result of one integration step: the new state is written to `nxt`; `s1` is
@@ -1825,6 +1832,43 @@ __global__ void __launch_bounds__(kBlock) k_rayborn_rho(int64_t n, int n_freq, c
     if (lane == 0) rho[i] = acc;
 }
 
+// Free march without a ring (the ray equations of Sec. 3.2 followed for a fixed
+// number of steps, as in the radius experiment of Sec. 4.1).  One lane per ray:
+// ray i starts at x0[i] (metres from the grid centre) along d0[i] (normalised
+// here) and takes n_steps steps; the start and every step's end point are
+// written to pts[i] in metres.  From the first point outside the node
+// rectangle on (or for a zero or non-finite direction) the points are NaN and
+// the ray stops.
+template <class R, bool COMP, int INTEG, bool BSP>
+__global__ void __launch_bounds__(kBlock)
+    k_march(Medium<R> M, Geo g, int64_t n_rays, const double *__restrict__ x0, const double *__restrict__ d0,
+            int n_steps, double *__restrict__ pts)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_rays) return;
+    const double ddx = d0[2 * i], ddy = d0[2 * i + 1];
+    const double nrm = sqrt(ddx * ddx + ddy * ddy);
+    Ray<R> ray;
+    ray_set<R, COMP>(ray, x0[2 * i] / g.h + g.cx, x0[2 * i + 1] / g.h + g.cy, ddx / nrm, ddy / nrm);
+    const R ds = (R)g.ds;
+    Slot<R> C[3];
+    if (!BSP) slots_prime(M, C, ray, ds, INTEG);
+    double *o = pts + (size_t)i * (size_t)(n_steps + 1) * 2;
+    bool out = false;
+    for (int k = 0; k <= n_steps; k++) {
+        if (k > 0 && !out) {
+            Ray<R> nxt;
+            (void)ray_step<R, COMP, INTEG, BSP>(M, C, ray, nxt, ds);
+            ray = nxt;
+        }
+        const double u = (double)ray.uh + (double)ray.ul, v = (double)ray.vh + (double)ray.vl;
+        const double dl = (double)ray.dxh + (double)ray.dxl;
+        out = out || !(u >= 0.0 && u <= g.nx - 1.0 && v >= 0.0 && v <= g.ny - 1.0 && dl == dl);
+        o[2 * k] = out ? (double)NAN : (u - g.cx) * g.h;
+        o[2 * k + 1] = out ? (double)NAN : (v - g.cy) * g.h;
+    }
+}
+
 }  // namespace
 
 // ===================================================================== plan ==
@@ -2281,6 +2325,20 @@ int batch_upload(rtx_batch_s *Bt)
 }  // namespace
 
 // ====================================================================== ABI ==
+template <class R, bool COMP>
+int launch_march(rtx_plan_s *P, int64_t n_rays, const double *x0, const double *d0, int n_steps, double *pts,
+                 hipStream_t s)
+{
+    Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
+    Geo g = make_geo(P);
+    auto kern = P->bsp ? (P->opts.integ == RTX_RK4 ? k_march<R, COMP, 4, true> : k_march<R, COMP, 2, true>)
+                       : (P->opts.integ == RTX_RK4 ? k_march<R, COMP, 4, false> : k_march<R, COMP, 2, false>);
+    const unsigned blocks = (unsigned)((n_rays + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, M, g, n_rays, x0, d0, n_steps, pts);
+    HIP_TRY(hipGetLastError());
+    return RTX_OK;
+}
+
 extern "C" {
 
 const char *rtx_last_error(void) { return g_last_error.c_str(); }
@@ -2417,6 +2475,21 @@ int rtx_trace_rays(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_
     rc = fan ? launch_fan<double, false>(P, A, s) : launch_trace<double, false>(P, A, s);
     if (rc || !w_rowptr) return rc;
     return emit_weights<double, false>(P, A, w_rowptr, w_col, (double *)w_val, nnz_cap, s);
+}
+
+int rtx_march_free(rtx_plan P, const double *c, int64_t n_rays, const double *x0, const double *d0,
+                   int32_t n_steps, double *pts, void *stream)
+{
+    g_last_error.clear();
+    if (!P) return fail(RTX_E_ARG, "null plan");
+    if (n_rays < 0 || n_rays > ((int64_t)1 << 31) - kBlock) return fail(RTX_E_ARG, "bad n_rays %lld", (long long)n_rays);
+    if (n_steps < 0 || n_steps >= (1 << 30)) return fail(RTX_E_ARG, "bad n_steps %d", n_steps);
+    if (n_rays > 0 && (!x0 || !d0 || !pts)) return fail(RTX_E_ARG, "x0, d0 and pts are required");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = pack(P, c, s);
+    if (rc || n_rays == 0) return rc;
+    if (P->opts.prec == RTX_F32C) return launch_march<float, true>(P, n_rays, x0, d0, n_steps, pts, s);
+    return launch_march<double, false>(P, n_rays, x0, d0, n_steps, pts, s);
 }
 
 int rtx_tof_forward(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_pairs, double *theta,

@@ -1,8 +1,10 @@
 """The cubic B-spline medium (Sec. 3.3) on the HIP path, through the C ABI,
 against the oracle's B-spline medium: fixed-angle traces pair by pair, linked
-traces by re-tracing the GPU's angles, the Section 4.2 fish-eye acoustic-length
-experiment at ds/dx = 1 with both integrators, and the calls a B-spline plan
-refuses (adjoint, path weights, changing the interpolation)."""
+traces by re-tracing the GPU's angles, the paper's Section 4 fish-eye
+experiments (acoustic length, Sec. 4.2, over a sweep of ds/dx; radius
+deviation of the free-marched ray, Sec. 4.1) with both integrators, and the
+calls a B-spline plan refuses (adjoint, path weights, changing the
+interpolation)."""
 import json
 import math
 import os
@@ -143,6 +145,80 @@ def test_paper_fisheye_acoustic_length_on_gpu(rtx, prec, integ):
     print(f"\nRE_al {prec} {integ}: GPU {re_al:.3e} %, oracle {re_ref:.3e} %", flush=True)
     assert abs(re_al) < {"rk4": 0.003, "heun": 0.005}[integ]
     assert np.max(out["miss_px"]) * dx < 2e-4 * a
+
+
+def _golden():
+    with open(os.path.join(HERE, "golden", "fisheye_paper.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+@pytest.mark.parametrize("integ", ["rk4", "heun"])
+def test_paper_fisheye_acoustic_length_ds_sweep(rtx, prec, integ):
+    """Section 4.2's deviation RE_al over ds/dx = 1/4 .. 2 (the paper plots it
+    against ds/dx): GPU equal to the oracle at every step size, and the error
+    second order in ds (the trapezoid quadrature dominates the B-spline field's
+    error on this grid)."""
+    g = _golden()
+    a, dx = g["a"], g["dx_over_a"] * g["a"]
+    n = 2 * int(math.ceil(1.1 * a / dx)) + 1
+    c = synth.fisheye(n, n, dx, c0=1.0, R=a)
+    ring = (4, a, math.pi / 2)
+    th = np.linspace(*g["al_theta_range"], g["al_n_rays"])
+    pairs = np.tile(np.array([[0, 2]], np.int32), (len(th), 1))
+    plan = rtx.Plan(n, n, dx, *ring, prec=prec, integ=integ, max_pairs=len(pairs), interp="bspline")
+    plan.set_medium(_dev(c))
+    res = []
+    for ds in (0.25, 0.5, 1.0, 2.0):
+        out = plan.trace(None, pairs=_dev(pairs), theta=_dev(th), fixed=True, ds_px=ds)
+        T = _np(out["tof"])
+        assert np.all(_np(out["status"]) == oracle.LINKED)
+        ref = oracle.trace(_bsp(c, dx), ring, pairs, theta=th, fixed=True, integ=integ, ds_px=ds)
+        res.append((np.mean((T - g["L_true"]) / g["L_true"]) * 100,
+                    np.mean((ref["tof"] - g["L_true"]) / g["L_true"]) * 100))
+    plan.close()
+    print(f"\nRE_al (%) {prec} {integ} at ds/dx 0.25, 0.5, 1, 2: GPU " + ", ".join("%.3e" % r[0] for r in res)
+          + "; oracle " + ", ".join("%.3e" % r[1] for r in res), flush=True)
+    for gpu, ref in res:
+        assert abs(gpu - ref) < (1e-9 if prec == "f64" else 5e-5)
+    if prec == "f64":  # FP32 rounding (~1e-5 %) blurs the ratios at the smallest steps
+        for (r1, _), (r2, _) in zip(res, res[1:]):
+            assert 3.0 < r2 / r1 < 5.0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+@pytest.mark.parametrize("integ", ["rk4", "heun"])
+def test_paper_fisheye_radius_deviation_on_gpu(rtx, prec, integ):
+    """Section 4.1 on the HIP path: the ray from [0, a] launched clockwise,
+    normal to x_c - x_p, circles x_c = [a, 0] with radius sqrt(2) a; marched
+    free over 1.2 turns at ds/dx = 1 and 1/2, point by point against the
+    oracle's march, and RE_rd over the first turn within the oracle's budget."""
+    g = _golden()
+    a, dx = g["a"], g["dx_over_a"] * g["a"]
+    n = 2 * int(math.ceil(2.6 * a / dx)) + 1
+    c = synth.fisheye(n, n, dx, c0=1.0, R=a)
+    plan = rtx.Plan(n, n, dx, 4, a, math.pi / 2, prec=prec, integ=integ, interp="bspline")
+    x0 = np.array(g["rd_start"])
+    d0 = np.array(g["rd_direction_clockwise"])
+    for ds in (1.0, 0.5):
+        circ = 2 * math.pi * g["R_true"] / dx
+        n_steps = int(1.2 * circ / ds)
+        pts = _np(plan.march(_dev(x0[None]), _dev(d0[None]), n_steps, c=_dev(c), ds_px=ds))[0]
+        ref = oracle.march_free(_bsp(c, dx), x0 / dx, d0, n_steps, ds_px=ds, integ=integ) * dx
+        dev_px = np.abs(pts - ref).max() / dx
+        assert dev_px < (1e-9 if prec == "f64" else 2e-3), dev_px
+        dist0 = np.linalg.norm(pts - x0, axis=1)
+        far = np.nonzero(dist0 > 10 * ds * dx)[0][0]
+        M = far + np.nonzero(dist0[far:] < ds * dx)[0][0]
+        rad = np.linalg.norm(pts[1:M + 1] - np.array(g["rd_centre"]), axis=1)
+        re_rd = np.mean(np.abs(rad - g["R_true"]) / g["R_true"]) * 100
+        print(f"\nRE_rd {prec} {integ} ds/dx {ds}: {re_rd:.3e} % (max point deviation from the oracle "
+              f"{dev_px:.1e} px)", flush=True)
+        # FP32 marching holds the radius to ~5e-7 relative (a few ulps of the
+        # FP32 field and curvature), above RK4's truncation error on this ray
+        bound = {"rk4": 2e-5 if prec == "f64" else 1e-4, "heun": 0.02}[integ]
+        assert re_rd < bound * ds ** (0 if integ == "rk4" else 2)
+    plan.close()
 
 
 def test_bspline_plan_refuses_bilinear_only_calls(rtx):

@@ -211,6 +211,50 @@ def test_status_paths_match_oracle(rtx, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+@pytest.mark.parametrize("integ", ["rk4", "heun"])
+def test_free_march_matches_oracle(rtx, prec, integ):
+    """rtx_march_free: 301 rays (two blocks and a ragged tail) from random points
+    in random directions of random length, 500 steps; many leave the grid.
+    Point by point against the oracle's free march while both are on the grid;
+    the GPU ray stops (NaN) at its first point outside the node rectangle, and a
+    zero direction gives NaN throughout."""
+    n, h = 96, 0.5e-3
+    c = _gauss(n, h, seed=41)
+    ring = (16, 0.45 * n * h * 0.9, 0.0)
+    rng = np.random.default_rng(41)
+    nr, steps = 301, 500
+    x0 = rng.uniform(-0.3, 0.3, (nr, 2)) * n * h
+    ang = rng.uniform(0, 2 * np.pi, nr)
+    d0 = np.stack([np.cos(ang), np.sin(ang)], 1) * rng.uniform(0.5, 2.0, (nr, 1))
+    d0[7] = 0.0
+    plan = rtx.Plan(n, n, h, *ring, prec=prec, integ=integ, max_pairs=1)
+    pts = _np(plan.march(_dev(x0), _dev(d0), steps, c=_dev(c)))
+    empty = plan.march(_dev(np.zeros((0, 2))), _dev(np.zeros((0, 2))), steps)
+    plan.close()
+    assert empty.shape == (0, steps + 1, 2)
+    assert np.all(np.isnan(pts[7]))
+    half = (n - 1) / 2 * h
+    med = oracle.grid_medium(c, h)
+    tol = (1e-9 if prec == "f64" else 2e-3) * h
+    n_left = 0
+    for i in range(nr):
+        if i == 7:
+            continue
+        ref = oracle.march_free(med, x0[i] / h, d0[i], steps, integ=integ) * h
+        fin = np.isfinite(pts[i, :, 0])
+        k = int(np.argmin(fin)) if not fin.all() else steps + 1
+        assert fin[:k].all() and not fin[k:].any()
+        assert np.all(np.abs(pts[i, :k]) <= half)
+        both = fin & np.isfinite(ref[:, 0])
+        assert both[:k].sum() >= min(k, 10)
+        assert np.abs(pts[i][both] - ref[both]).max() < tol, (i, np.abs(pts[i][both] - ref[both]).max() / h)
+        if k <= steps:  # the GPU stopped: the oracle's point there is off the grid too (or already NaN)
+            n_left += 1
+            assert not np.isfinite(ref[k, 0]) or np.abs(ref[k]).max() > half - 1e-9 * h
+    assert n_left > 50
+
+
 def test_argument_errors(rtx):
     with pytest.raises(rtx.RtxError):
         rtx.Plan(64, 64, 1e-3, 16, 0.040)  # ring does not fit the grid
