@@ -70,6 +70,7 @@ def _load(path):
     L.or_adjoint.argtypes = [C.c_int, C.c_int, C.c_double, _dp, C.c_int, C.c_double, C.c_double, C.c_int,
                              C.c_double, C.c_int, C.c_int, _ip, _dp, _bp, _dp, C.c_int, _dp]
     L.or_rayborn_rho.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
+    L.or_sart.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int64), _ip, _dp, _dp, _dp, C.c_int, C.c_double]
     _lib = L
 
 
@@ -274,3 +275,19 @@ def rayborn_rho(tof, freqs, resid):
     rho = np.empty(n)
     lib().or_rayborn_rho(n, nf, _d(tof), _d(freqs), _d(ri), _d(rho))
     return rho
+
+
+def sart(rowptr, cols, vals, b, x0, n_iter, lam=1.0):
+    """n_iter SART iterations on W x = b (W as CSR) from x0; returns x."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64, copy=True).ravel()
+    if len(rowptr) != len(b) + 1 or len(cols) != rowptr[-1] or len(vals) != rowptr[-1]:
+        raise ValueError("inconsistent CSR")
+    rc = lib().or_sart(len(b), len(x), rowptr.ctypes.data_as(C.POINTER(C.c_int64)), _i(cols), _d(vals), _d(b),
+                       _d(x), int(n_iter), float(lam))
+    if rc:
+        raise ValueError("column index out of range")
+    return x

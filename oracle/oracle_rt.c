@@ -1046,3 +1046,45 @@ int or_fan_cubic(const double *G, const double *TH, int m, int a, double *th)
 {
     return fan_cubic(G, TH, m, a, th);
 }
+
+/* SART, the default solver of the linearised ToF subproblem (Sec. 3.1; the
+   simultaneous algebraic reconstruction technique of Andersen and Kak).  With
+   the system matrix W (CSR, n_rows x n_cols), its row sums M_i = sum_j W_ij and
+   column sums V_j = sum_i W_ij, each of the n_iter iterations sets
+     x_j <- x_j + lambda / V_j * sum_i W_ij (b_i - sum_l W_il x_l) / M_i
+   for every column with V_j != 0, all from the x of the previous iteration
+   (the simultaneous update); rows with M_i == 0 take no part.  x is updated in
+   place.  Returns -1 on a column index out of range. */
+int or_sart(int n_rows, int n_cols, const int64_t *rowptr, const int32_t *col, const double *val, const double *b,
+            double *x, int n_iter, double lambda)
+{
+    double *M = (double *)calloc((size_t)n_rows, sizeof(double));
+    double *V = (double *)calloc((size_t)n_cols, sizeof(double));
+    double *upd = (double *)malloc(sizeof(double) * (size_t)n_cols);
+    int rc = 0;
+    for (int i = 0; i < n_rows && !rc; i++)
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; k++) {
+            if (col[k] < 0 || col[k] >= n_cols) {
+                rc = -1;
+                break;
+            }
+            M[i] += val[k];
+            V[col[k]] += val[k];
+        }
+    for (int it = 0; it < n_iter && !rc; it++) {
+        for (int j = 0; j < n_cols; j++) upd[j] = 0.0;
+        for (int i = 0; i < n_rows; i++) {
+            if (M[i] == 0.0) continue;
+            double proj = 0.0;
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; k++) proj += val[k] * x[col[k]];
+            double r = (b[i] - proj) / M[i];
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; k++) upd[col[k]] += val[k] * r;
+        }
+        for (int j = 0; j < n_cols; j++)
+            if (V[j] != 0.0) x[j] += lambda * upd[j] / V[j];
+    }
+    free(M);
+    free(V);
+    free(upd);
+    return rc;
+}

@@ -44,6 +44,12 @@ MUTATIONS = {
                                   "const double *g = G + a - 1, *t = TH + a;"),
     "fan_cubic_bracket_ends": ("double lo = t[1] < t[2] ? t[1] : t[2], hi = t[1] < t[2] ? t[2] : t[1];",
                                "double lo = t[0] < t[3] ? t[0] : t[3], hi = t[0] < t[3] ? t[3] : t[0];"),
+    "sart_rowsum_dropped": ("double r = (b[i] - proj) / M[i];", "double r = (b[i] - proj);"),
+    "sart_colsum_dropped": ("if (V[j] != 0.0) x[j] += lambda * upd[j] / V[j];",
+                            "if (V[j] != 0.0) x[j] += lambda * upd[j];"),
+    "sart_sequential_update": ("for (int64_t k = rowptr[i]; k < rowptr[i + 1]; k++) upd[col[k]] += val[k] * r;",
+                               "for (int64_t k = rowptr[i]; k < rowptr[i + 1]; k++) x[col[k]] += lambda * val[k] * r "
+                               "/ V[col[k]];"),
     "fan_target_wrong_receiver": ("G[j - 1] = row[j - 1].st == ST_LINKED ? (row[j - 1].g + Dj) - Dr : NAN;",
                                   "G[j - 1] = row[j - 1].st == ST_LINKED ? row[j - 1].g - Dr : NAN;"),
 }
@@ -72,6 +78,10 @@ PINS = [
     lambda o: P.test_fan_cubic_falls_back(o),
     lambda o: P.test_fan_start_same_roots_fewer_rays(o),
     lambda o: P.test_fan_start_fisheye_reversed_orientation(o),
+    lambda o: P.test_sart_one_row_is_exact(o),
+    lambda o: P.test_sart_step_is_preconditioned_gradient_step(o),
+    lambda o: P.test_sart_consistent_system_converges(o),
+    lambda o: P.test_sart_zero_rows_and_columns_take_no_part(o),
 ]
 
 

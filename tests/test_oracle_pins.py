@@ -561,3 +561,77 @@ def test_fan_cubic_falls_back(orc):
     far = np.array([-1.0, -0.999, -1e-9, 1.0, 1.0001, 1.0002])
     r = orc.fan_cubic(far, TH, 2)
     assert r is None or TH[2] < r < TH[3]
+
+
+# ---------------------------------------------------------------- SART ------
+def _csr(W):
+    rowptr = np.zeros(W.shape[0] + 1, np.int64)
+    cols, vals = [], []
+    for i, row in enumerate(W):
+        nz = np.nonzero(row)[0]
+        cols.append(nz)
+        vals.append(row[nz])
+        rowptr[i + 1] = rowptr[i] + len(nz)
+    return rowptr, np.concatenate(cols).astype(np.int32), np.concatenate(vals)
+
+
+def _rand_system(seed, n_rows, n_cols, density):
+    rng = np.random.default_rng(seed)
+    W = rng.uniform(0.1, 1.0, (n_rows, n_cols)) * (rng.uniform(size=(n_rows, n_cols)) < density)
+    W[np.arange(n_rows), rng.integers(0, n_cols, n_rows)] += 0.5  # no empty row
+    W[rng.integers(0, n_rows, n_cols), np.arange(n_cols)] += 0.5  # no empty column
+    return rng, W
+
+
+def test_sart_one_row_is_exact(orc):
+    """A single equation: from x = 0 with lambda = 1 every unknown of the row
+    becomes b / M (each column sum is that column's own weight), which meets the
+    equation exactly; unknowns outside the row keep their value."""
+    W = np.array([[0.3, 0.0, 1.2, 0.5, 0.0]])
+    x = orc.sart(*_csr(W), [2.0], np.array([0.0, 7.0, 0.0, 0.0, -1.0]), 1, 1.0)
+    np.testing.assert_allclose(x, [1.0, 7.0, 1.0, 1.0, -1.0], rtol=1e-15)
+    # a second iteration leaves the solution where it is
+    np.testing.assert_allclose(orc.sart(*_csr(W), [2.0], x, 1, 1.0), x, rtol=1e-15)
+
+
+def test_sart_step_is_preconditioned_gradient_step(orc):
+    """One SART iteration is x - lambda V^-1 grad f(x) with the row-sum weighted
+    least-squares misfit f(x) = 1/2 sum_i (b_i - W_i x)^2 / M_i and column sums V
+    (Andersen and Kak's simultaneous update); the gradient here is taken by
+    central finite differences of f."""
+    rng, W = _rand_system(61, 30, 20, 0.3)
+    b = rng.standard_normal(30)
+    x0 = rng.standard_normal(20)
+    x1 = orc.sart(*_csr(W), b, x0, 1, 0.7)
+    M, V = W.sum(1), W.sum(0)
+
+    def f(x):
+        return 0.5 * np.sum((b - W @ x) ** 2 / M)
+
+    e = 1e-6
+    grad = np.array([(f(x0 + e * u) - f(x0 - e * u)) / (2 * e) for u in np.eye(20)])
+    np.testing.assert_allclose(x1 - x0, -0.7 * grad / V, rtol=1e-6, atol=1e-9)
+
+
+def test_sart_consistent_system_converges(orc):
+    """A consistent system of full column rank: the iteration (0 < lambda < 2)
+    converges to its unique solution."""
+    rng, W = _rand_system(62, 60, 25, 0.4)
+    x_true = rng.uniform(-1, 1, 25)
+    x = orc.sart(*_csr(W), W @ x_true, np.zeros(25), 4000, 1.0)
+    assert np.abs(x - x_true).max() < 1e-8
+
+
+def test_sart_zero_rows_and_columns_take_no_part(orc):
+    """An empty row (a ray that never reached the ring) is ignored whatever its
+    datum, and an unknown no ray touches keeps its value."""
+    rng, W = _rand_system(63, 12, 9, 0.4)
+    b = rng.standard_normal(12)
+    W0 = np.insert(W, 5, 0.0, axis=0)
+    W0 = np.insert(W0, 3, 0.0, axis=1)
+    b0 = np.insert(b, 5, 1e30)
+    x0 = np.insert(np.zeros(9), 3, 7.0)
+    x = orc.sart(*_csr(W0), b0, x0, 5, 1.3)
+    ref = orc.sart(*_csr(W), b, np.zeros(9), 5, 1.3)
+    assert x[3] == 7.0
+    np.testing.assert_allclose(np.delete(x, 3), ref, rtol=1e-14)
