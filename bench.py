@@ -96,6 +96,48 @@ def run_gpu(prec, c_host, cfg, steps, warmup, resid_host, fan=True):
     return res, out
 
 
+def run_sart(c_host, cfg, iters=10):
+    """SART (Sec. 3.1) on the workload's own FP32 system matrix: the once-per-
+    call setup (sums and the device transpose of W) and the time of one
+    iteration (residual pass over the rows, back-projection pass over the
+    columns), with its HBM rate against the algorithmic bytes of an iteration."""
+    import torch
+
+    import paper_2511_18511_amd as rtx
+
+    dev = torch.device("cuda", 0)
+    plan = rtx.Plan(cfg["nx"], cfg["ny"], cfg["h"], cfg["n_elem"], cfg["radius"], cfg["phi0"], prec="f32c",
+                    integ=cfg["integ"], ds_px=cfg["ds_px"], tol_px=cfg["tol_px"], max_marches=cfg["max_marches"])
+    out = plan.trace(torch.from_numpy(c_host).to(dev), weights=True, fan=False)
+    rp, col, val = out["w_rowptr"], out["w_col"], out["w_val"]
+    n_rows, nnz, nodes = rp.shape[0] - 1, col.shape[0], cfg["nx"] * cfg["ny"]
+    b = torch.from_numpy(np.random.default_rng(5).standard_normal(n_rows) * 1e-6).to(dev)
+    x = torch.zeros(cfg["ny"], cfg["nx"], dtype=torch.float64, device=dev)
+    plan.sart(rp, col, val, b, x=x, n_iter=3)
+
+    def timed(n_iter):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        plan.sart(rp, col, val, b, x=x, n_iter=n_iter)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    t1 = min(timed(1) for _ in range(3))
+    tn = min(timed(1 + iters) for _ in range(3))
+    per = (tn - t1) / iters  # one iteration: a CSR residual pass and a CSC back-projection pass
+    setup = t1 - per  # row/column sums and the transpose, once per call
+    plan.close()
+    # per iteration: W's columns/values in both layouts (int32 + FP32 each),
+    # rowptr/b/M/r per row, colptr/V/x per node
+    bytes_it = 2 * nnz * 8 + n_rows * 32 + nodes * 32
+    ms = per * iters
+    return {"rows": int(n_rows), "nnz": int(nnz), "iterations": iters, "setup_ms": setup, "ms_per_iteration": ms / iters,
+            "bytes_per_iteration": int(bytes_it), "achieved_GBs": bytes_it / (ms / iters * 1e-3) / 1e9,
+            "vs_hbm_peak_frac": bytes_it / (ms / iters * 1e-3) / 1e9 / PEAK_HBM_GBS}
+
+
 def cpu_baseline(c, cfg, resid, max_seconds=30.0):
     """The FP64 oracle on the host cores: linked trace + adjoint of the same
     workload, pairs split over a thread pool (the oracle releases the GIL)."""
@@ -162,6 +204,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--fan-only", action="store_true", help="skip the straight-start comparison runs")
+    ap.add_argument("--no-sart", action="store_true", help="skip the SART measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device copy (the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profile)")
@@ -205,6 +248,10 @@ def main():
               "achieved_GBs": gbytes / t_s / 1e9, "vs_hbm_peak_frac": gbytes / t_s / 1e9 / PEAK_HBM_GBS}
 
     roof["traffic"] = measured_traffic()
+    sart = None if args.no_sart else run_sart(c, cfg)
+    if sart:
+        print(f"# SART: setup {sart['setup_ms']:.3f} ms, {sart['ms_per_iteration']:.3f} ms/iteration on "
+              f"{sart['nnz']} entries ({sart['achieved_GBs']:.0f} GB/s)", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(c, cfg, resid)
     line = {
         "metric": "linked rays/s (ToF+path) and adjoint time; FP32-comp vs FP64 plain, same GPU",
@@ -230,6 +277,7 @@ def main():
         "f32c_over_f64": (f32["rays_per_s"] / f64["rays_per_s"]) if f64 else None,
         "straight_start": {p: runs[(p, False)] for p, fan in runs if not fan},
         "gather": gather,
+        "sart": sart,
     }
     print(json.dumps(line))
 

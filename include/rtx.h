@@ -167,6 +167,34 @@ int rtx_trace_rays(rtx_plan plan, const double *c, const int32_t *pairs, int64_t
 int rtx_tof_forward(rtx_plan plan, const double *c, const int32_t *pairs, int64_t n_pairs, double *theta,
                     double *tof, int8_t *status, void *stream);
 
+/* SART (Sec. 3.1: the default solver of the linearised ToF subproblem; the
+   simultaneous algebraic reconstruction technique of Andersen and Kak) on the
+   system matrix W of rtx_trace_rays: n_iter iterations of
+     x_j <- x_j + lambda / V_j * sum_i W_ij (b_i - sum_l W_il x_l) / M_i
+   with row sums M_i and column sums V_j of W, all columns updated from the
+   previous iterate; rows with M_i == 0 (empty rows) and columns with V_j == 0
+   (nodes no ray touches) take no part.
+     w_rowptr [n_rows + 1] int64, w_col [nnz] int32, w_val [nnz] float
+              (RTX_F32C plans) or double (RTX_F64): CSR as emitted by
+              rtx_trace_rays (device); entries k outside [0, nnz) and columns
+              outside [0, nx * ny) are left out
+     b        [n_rows] float64 (device): data, e.g. travel-time residuals (s)
+     x        [ny * nx] float64 (device, in/out): start and result, e.g. the
+              slowness update (s/m); column index = iy * nx + ix
+   The call transposes W once (CSC, built on the device; the order of the
+   entries inside a column, and so the rounding of the column sums, varies
+   between runs) and then streams W by rows and by columns each iteration;
+   arithmetic is FP64.  w_rowptr must be non-decreasing (otherwise the result
+   is undefined; memory accesses stay in bounds).  Plan-owned scratch: about
+   (2 max_pairs + 2.5 nx ny) x 8 bytes on first use, and (4 + value size) x nnz
+   bytes for the transpose, grown when a larger W arrives (a call that grows
+   it frees and allocates).
+   Errors: n_rows < 0 or > max_pairs, nnz < 0, n_iter < 0, lambda outside
+   (0, 2), missing buffers -> RTX_E_ARG (nothing enqueued); RTX_E_NOMEM.
+   n_rows == 0 or n_iter == 0 leaves x unchanged. */
+int rtx_sart(rtx_plan plan, int64_t n_rows, int64_t nnz, const int64_t *w_rowptr, const int32_t *w_col,
+             const void *w_val, const double *b, double *x, int32_t n_iter, double lambda, void *stream);
+
 /* Free march without a ring: the ray equations of Sec. 3.2 followed for a
    fixed number of steps, as in the trajectory (radius) experiment of Sec. 4.1.
      x0   [n_rays][2] float64, device: start points, metres from the grid centre

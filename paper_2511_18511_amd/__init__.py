@@ -136,6 +136,22 @@ class Plan:
         B.rtx_march_free(self._handle, _ptr(c), n, _ptr(x0), _ptr(d0), int(n_steps), _ptr(pts), _stream())
         return pts
 
+    def sart(self, w_rowptr, w_col, w_val, b, x=None, n_iter=10, lam=1.0):
+        """SART iterations (Sec. 3.1) on W x = b with W as returned by
+        weights()/trace(weights=True); x (float64 [ny, nx] device, updated in
+        place) starts at zero when None.  Returns x."""
+        n = b.shape[0]
+        _dev_check(w_rowptr, torch.int64, (n + 1,), "w_rowptr")
+        _dev_check(w_col, torch.int32, None, "w_col")
+        _dev_check(w_val, self.real, (w_col.shape[0],), "w_val")
+        _dev_check(b, torch.float64, (n,), "b")
+        if x is None:
+            x = torch.zeros(self.ny, self.nx, dtype=torch.float64, device=b.device)
+        _dev_check(x, torch.float64, (self.ny, self.nx), "x")
+        B.rtx_sart(self._handle, n, w_col.shape[0], _ptr(w_rowptr), _ptr(w_col), _ptr(w_val), _ptr(b), _ptr(x),
+                   int(n_iter), float(lam), _stream())
+        return x
+
     def weights(self, theta, pairs=None, **over):
         """System-matrix rows W_ij = h sum_m w_m phi_j(p_m) of the rays traced at
         the given angles, as CSR device tensors (rowptr int64 [n+1], col int32

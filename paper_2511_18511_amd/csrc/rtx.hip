@@ -1869,6 +1869,189 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
+// ------------------------------------------------------------------- SART --
+// SART on the system matrix W (Sec. 3.1's default solver of the linearised ToF
+// subproblem).  Every step streams W with one wave per row (CSR) or per column
+// (CSC), the line's entries read by consecutive lanes, and gathers from a small
+// L2-resident vector:
+//   once per call: row sums M_i and column counts (CSR pass), column offsets
+//   (one-block scan), the transpose (CSR pass placing each entry in its
+//   column; the order inside a column varies between runs), column sums V_j
+//   (CSC pass);
+//   per iteration: r_i = (b_i - W_i x) / M_i (CSR pass), then
+//   x_j += lambda / V_j sum_i W_ij r_i (CSC pass).
+// No float atomics; all sums in FP64.  Entries whose column lies outside
+// [0, n_nodes) are left out.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fill(T *__restrict__ a, int64_t n, T v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// M_i and the entry count of every column.
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_sart_count(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col, const R *__restrict__ val,
+                 int64_t n_rows, int64_t nnz, int64_t n_nodes, double *__restrict__ M, unsigned *__restrict__ cnt)
+{
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (i >= n_rows) return;
+    double m = 0.0;
+    const int64_t k1 = min(rowptr[i + 1], nnz);
+    for (int64_t k0 = max(rowptr[i], (int64_t)0) + lane; k0 < k1; k0 += 4 * 64) {
+        int32_t j[4];
+        R w[4];
+        for (int u = 0; u < 4; u++) {  // four entries in flight per lane
+            const int64_t k = k0 + 64 * u;
+            j[u] = k < k1 ? col[k] : -1;
+            w[u] = k < k1 ? val[k] : (R)0;
+        }
+        for (int u = 0; u < 4; u++) {
+            if ((uint64_t)j[u] >= (uint64_t)n_nodes) continue;
+            m += (double)w[u];
+            atomicAdd(cnt + j[u], 1u);
+        }
+    }
+    m = wave_sum(m);
+    if (lane == 0) M[i] = m;
+}
+
+// Exclusive scan of the counts into colptr[0..n] (one block); clears cnt for
+// use as the fill cursor.
+__global__ void __launch_bounds__(1024) k_sart_scan(unsigned *__restrict__ cnt, int64_t n, int64_t *__restrict__ colptr)
+{
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024, lo = min((int64_t)t * per, n), hi = min(lo + per, n);
+    int64_t sum = 0;
+    for (int64_t j = lo; j < hi; j++) sum += cnt[j];
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scan of the parts
+        const int64_t v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = t ? part[t - 1] : 0;
+    for (int64_t j = lo; j < hi; j++) {
+        colptr[j] = run;
+        run += cnt[j];
+        cnt[j] = 0;
+    }
+    if (t == 1023) colptr[n] = part[1023];
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_sart_place(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col, const R *__restrict__ val,
+                 int64_t n_rows, int64_t nnz, int64_t n_nodes, const int64_t *__restrict__ colptr,
+                 unsigned *__restrict__ cur, int32_t *__restrict__ crow, R *__restrict__ cval, int64_t cap)
+{
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (i >= n_rows) return;
+    const int64_t k1 = min(rowptr[i + 1], nnz);
+    for (int64_t k0 = max(rowptr[i], (int64_t)0) + lane; k0 < k1; k0 += 4 * 64) {
+        int32_t j[4];
+        R w[4];
+        int64_t pos[4];
+        for (int u = 0; u < 4; u++) {  // four entries in flight per lane
+            const int64_t k = k0 + 64 * u;
+            j[u] = k < k1 ? col[k] : -1;
+            w[u] = k < k1 ? val[k] : (R)0;
+        }
+        for (int u = 0; u < 4; u++)
+            pos[u] = (uint64_t)j[u] < (uint64_t)n_nodes ? colptr[j[u]] + atomicAdd(cur + j[u], 1u) : cap;
+        for (int u = 0; u < 4; u++) {
+            if (pos[u] >= cap) continue;  // an invalid column, or a row pointer that is not monotone
+            crow[pos[u]] = (int32_t)i;
+            cval[pos[u]] = w[u];
+        }
+    }
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_sart_colsum(const int64_t *__restrict__ colptr,
+                                                        const R *__restrict__ cval, int64_t n_nodes, int64_t cap,
+                                                        double *__restrict__ V)
+{
+    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (j >= n_nodes) return;
+    double v = 0.0;
+    const int64_t k1 = min(colptr[j + 1], cap);
+    for (int64_t k = colptr[j] + lane; k < k1; k += 64) v += (double)cval[k];
+    v = wave_sum(v);
+    if (lane == 0) V[j] = v;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_sart_resid(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col, const R *__restrict__ val,
+                 int64_t n_rows, int64_t nnz, int64_t n_nodes, const double *__restrict__ b,
+                 const double *__restrict__ M, const double *__restrict__ x, double *__restrict__ r)
+{
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (i >= n_rows) return;
+    const double m = M[i];
+    double proj = 0.0;
+    const int64_t k1 = min(rowptr[i + 1], nnz);
+    if (m != 0.0)
+        for (int64_t k0 = max(rowptr[i], (int64_t)0) + lane; k0 < k1; k0 += 4 * 64) {
+            int32_t j[4];
+            R w[4];
+            for (int u = 0; u < 4; u++) {  // four entries in flight per lane
+                const int64_t k = k0 + 64 * u;
+                j[u] = k < k1 ? col[k] : -1;
+                w[u] = k < k1 ? val[k] : (R)0;
+            }
+            double xv[4];
+            for (int u = 0; u < 4; u++) xv[u] = (uint64_t)j[u] < (uint64_t)n_nodes ? x[j[u]] : 0.0;
+            for (int u = 0; u < 4; u++) proj = fma((double)w[u], xv[u], proj);
+        }
+    proj = wave_sum(proj);
+    if (lane == 0) r[i] = m != 0.0 ? (b[i] - proj) / m : 0.0;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_sart_back(const int64_t *__restrict__ colptr, const int32_t *__restrict__ crow, const R *__restrict__ cval,
+                int64_t n_nodes, int64_t cap, const double *__restrict__ r, const double *__restrict__ V,
+                double lambda, double *__restrict__ x)
+{
+    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (j >= n_nodes) return;
+    const double v = V[j];
+    if (v == 0.0) return;
+    double u = 0.0;
+    const int64_t k1 = min(colptr[j + 1], cap);
+    for (int64_t k0 = colptr[j] + lane; k0 < k1; k0 += 4 * 64) {
+        int32_t q[4];
+        R w[4];
+        for (int t = 0; t < 4; t++) {  // four entries in flight per lane
+            const int64_t k = k0 + 64 * t;
+            q[t] = k < k1 ? crow[k] : -1;
+            w[t] = k < k1 ? cval[k] : (R)0;
+        }
+        double rv[4];
+        for (int t = 0; t < 4; t++) rv[t] = q[t] >= 0 ? r[q[t]] : 0.0;
+        for (int t = 0; t < 4; t++) u = fma((double)w[t], rv[t], u);
+    }
+    u = wave_sum(u);
+    if (lane == 0) x[j] += lambda * u / v;
+}
+
 }  // namespace
 
 // ===================================================================== plan ==
@@ -1879,6 +2062,9 @@ struct rtx_plan_s {
     int64_t max_pairs;
     void *tab = nullptr;  // packed medium
     bool have_medium = false;
+    void *sart = nullptr;      // SART scratch: M, r [max_pairs]; V [nx*ny]; colptr [nx*ny+1]; counts
+    void *sart_csc = nullptr;  // SART transpose of W: rows (int32) and values, for sart_cap entries
+    int64_t sart_cap = 0;
     bool bsp = false;          // cubic B-spline interpolation (RTX_INTERP_BSPLINE)
     double *bsp_q = nullptr;   // [ny][nx] B-spline coefficients (FP64)
     unsigned long long *stats = nullptr;  // [3][kMaxBlocks][2]: trace, fan link pass, adjoint
@@ -2339,6 +2525,49 @@ int launch_march(rtx_plan_s *P, int64_t n_rays, const double *x0, const double *
     return RTX_OK;
 }
 
+template <class R>
+int launch_sart(rtx_plan_s *P, int64_t n_rows, int64_t nnz, const int64_t *rowptr, const int32_t *col, const R *val,
+                const double *b, double *x, int n_iter, double lambda, hipStream_t s)
+{
+    const int64_t nodes = (int64_t)P->grid.nx * P->grid.ny;
+    double *M = (double *)P->sart, *r = M + P->max_pairs, *V = r + P->max_pairs;
+    int64_t *colptr = (int64_t *)(V + nodes);
+    unsigned *cnt = (unsigned *)(colptr + nodes + 1);
+    // the transpose holds at most nnz entries: every kernel reads entries k < nnz only
+    if (nnz > P->sart_cap) {
+        if (P->sart_csc) (void)hipFree(P->sart_csc);
+        P->sart_csc = nullptr;
+        P->sart_cap = 0;
+        const int64_t cap = (nnz + 1) & ~(int64_t)1;  // even: keeps the value array 8-byte aligned
+        if (hipMalloc(&P->sart_csc, (sizeof(int32_t) + sizeof(R)) * (size_t)cap) != hipSuccess) {
+            P->sart_csc = nullptr;
+            return fail(RTX_E_NOMEM, "SART transpose allocation (%lld entries) failed", (long long)nnz);
+        }
+        P->sart_cap = cap;
+    }
+    int32_t *crow = (int32_t *)P->sart_csc;
+    R *cval = (R *)(crow + P->sart_cap);
+    const unsigned rb = (unsigned)((n_rows * 64 + kBlock - 1) / kBlock);
+    const unsigned cb = (unsigned)((nodes * 64 + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_fill<unsigned>, dim3((unsigned)((nodes + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, cnt,
+                       nodes, 0u);
+    hipLaunchKernelGGL(k_sart_count<R>, dim3(rb), dim3(kBlock), 0, s, rowptr, col, val, n_rows, nnz, nodes, M, cnt);
+    hipLaunchKernelGGL(k_sart_scan, dim3(1), dim3(1024), 0, s, cnt, nodes, colptr);
+    hipLaunchKernelGGL(k_sart_place<R>, dim3(rb), dim3(kBlock), 0, s, rowptr, col, val, n_rows, nnz, nodes,
+                       (const int64_t *)colptr, cnt, crow, cval, P->sart_cap);
+    hipLaunchKernelGGL(k_sart_colsum<R>, dim3(cb), dim3(kBlock), 0, s, (const int64_t *)colptr, (const R *)cval,
+                       nodes, P->sart_cap, V);
+    for (int it = 0; it < n_iter; it++) {
+        hipLaunchKernelGGL(k_sart_resid<R>, dim3(rb), dim3(kBlock), 0, s, rowptr, col, val, n_rows, nnz, nodes, b,
+                           (const double *)M, (const double *)x, r);
+        hipLaunchKernelGGL(k_sart_back<R>, dim3(cb), dim3(kBlock), 0, s, (const int64_t *)colptr,
+                           (const int32_t *)crow, (const R *)cval, nodes, P->sart_cap, (const double *)r,
+                           (const double *)V, lambda, x);
+    }
+    HIP_TRY(hipGetLastError());
+    return RTX_OK;
+}
+
 extern "C" {
 
 const char *rtx_last_error(void) { return g_last_error.c_str(); }
@@ -2391,6 +2620,8 @@ int rtx_plan_destroy(rtx_plan P)
     if (P->stats) (void)hipFree(P->stats);
     if (P->err) (void)hipFree(P->err);
     if (P->bsp_q) (void)hipFree(P->bsp_q);
+    if (P->sart) (void)hipFree(P->sart);
+    if (P->sart_csc) (void)hipFree(P->sart_csc);
     for (void *q : {(void *)P->f_g, (void *)P->f_T, (void *)P->f_L, (void *)P->f_st, P->f_seed})
         if (q) (void)hipFree(q);
     for (int k = 0; k < RTX_NUM_SLOTS; k++)
@@ -2475,6 +2706,35 @@ int rtx_trace_rays(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_
     rc = fan ? launch_fan<double, false>(P, A, s) : launch_trace<double, false>(P, A, s);
     if (rc || !w_rowptr) return rc;
     return emit_weights<double, false>(P, A, w_rowptr, w_col, (double *)w_val, nnz_cap, s);
+}
+
+int rtx_sart(rtx_plan P, int64_t n_rows, int64_t nnz, const int64_t *w_rowptr, const int32_t *w_col,
+             const void *w_val, const double *b, double *x, int32_t n_iter, double lambda, void *stream)
+{
+    g_last_error.clear();
+    if (!P) return fail(RTX_E_ARG, "null plan");
+    if (n_rows < 0 || n_rows > P->max_pairs)
+        return fail(RTX_E_ARG, "n_rows %lld outside [0, max_pairs = %lld]", (long long)n_rows,
+                    (long long)P->max_pairs);
+    if (n_iter < 0) return fail(RTX_E_ARG, "n_iter < 0");
+    if (nnz < 0 || nnz >= ((int64_t)1 << 40)) return fail(RTX_E_ARG, "bad nnz %lld", (long long)nnz);
+    if (!(lambda > 0.0 && lambda < 2.0)) return fail(RTX_E_ARG, "lambda must lie in (0, 2)");
+    if (!x || (n_rows > 0 && (!w_rowptr || !w_col || !w_val || !b)))
+        return fail(RTX_E_ARG, "x, and with rows w_rowptr, w_col, w_val and b, are required");
+    const int64_t nodes = (int64_t)P->grid.nx * P->grid.ny;
+    if (n_rows == 0 || n_iter == 0) return RTX_OK;
+    if (!P->sart) {
+        const size_t bytes = sizeof(double) * (2 * P->max_pairs + nodes) + sizeof(int64_t) * (nodes + 1) +
+                             sizeof(unsigned) * nodes;
+        if (hipMalloc(&P->sart, bytes) != hipSuccess) {
+            P->sart = nullptr;
+            return fail(RTX_E_NOMEM, "SART scratch allocation failed");
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (P->opts.prec == RTX_F32C)
+        return launch_sart<float>(P, n_rows, nnz, w_rowptr, w_col, (const float *)w_val, b, x, n_iter, lambda, s);
+    return launch_sart<double>(P, n_rows, nnz, w_rowptr, w_col, (const double *)w_val, b, x, n_iter, lambda, s);
 }
 
 int rtx_march_free(rtx_plan P, const double *c, int64_t n_rays, const double *x0, const double *d0,
