@@ -70,6 +70,8 @@ def _load(path):
     L.or_adjoint.argtypes = [C.c_int, C.c_int, C.c_double, _dp, C.c_int, C.c_double, C.c_double, C.c_int,
                              C.c_double, C.c_int, C.c_int, _ip, _dp, _bp, _dp, C.c_int, _dp]
     L.or_rayborn_rho.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
+    L.or_paraxial.argtypes = med + [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int, C.c_int, _ip,
+                                     _dp, _dp, _dp, _dp, _ip, _bp]
     L.or_sart.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int64), _ip, _dp, _dp, _dp, C.c_int, C.c_double]
     _lib = L
 
@@ -291,3 +293,22 @@ def sart(rowptr, cols, vals, b, x0, n_iter, lam=1.0):
     if rc:
         raise ValueError("column index out of range")
     return x
+
+
+def paraxial(medium, ring, pairs, theta, integ="rk4", ds_px=0.25, max_steps=0):
+    """Paraxial ray quantities at fixed launch angles: dict of dgdth, jac (m/rad),
+    amp (1/sqrt(m)), kmah (int32) and status."""
+    args, keep = _medium_args(medium)
+    n_elem, radius, phi0 = ring
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    n = pairs.shape[0]
+    out = {k: np.empty(n) for k in ("dgdth", "jac", "amp")}
+    out["kmah"] = np.empty(n, np.int32)
+    out["status"] = np.empty(n, np.int8)
+    rc = lib().or_paraxial(*args, int(n_elem), float(radius), float(phi0), _integ_code(integ), float(ds_px),
+                           int(max_steps), n, _i(pairs), _d(theta), _d(out["dgdth"]), _d(out["jac"]),
+                           _d(out["amp"]), _i(out["kmah"]), _b(out["status"]))
+    if rc:
+        raise ValueError("bad medium")
+    return out

@@ -1088,3 +1088,223 @@ int or_sart(int n_rows, int n_cols, const int64_t *rowptr, const int32_t *col, c
     free(upd);
     return rc;
 }
+
+/* ------------------------------------------------------------ paraxial ray -- */
+/* The paraxial ray (Sec. 3.5, the default way to the ray Jacobian): the
+   first-order perturbation (dx, dd) of a ray's position and direction caused by
+   a perturbation of its launch angle obeys the variational equations of the ray
+   ODE x' = d, d' = K(x, d) = -(G - (G.d) d) / c:
+     (dx)' = dd,
+     (dd)' = dK/dx dx + dK/dd dd,
+     dK/dd dd = ((G.dd) d + (G.d) dd) / c,
+     dK/dx dx = -(H dx - ((H dx).d) d) / c + (G - (G.d) d) (grad c . dx) / c^2,
+   with grad c the gradient of the interpolated c and H_ab = dG_a/dx_b the
+   derivative of the interpolated G (for the bilinear field: the derivatives of
+   the two separately interpolated fields).  The paper cites the system only;
+   this is its standard linearisation.  It is integrated with the ray by the
+   same Runge-Kutta scheme on the 8-component state, and the renormalisation of
+   d is linearised too: dd <- (dd - (n.dd) n) / |d|, n = d / |d|. */
+
+/* c, per-pixel G, grad c and H (row-major dG_a/dx_b) at pixel position (px, py). */
+static void medium_eval2(const Medium *m, double px, double py, double *c, double G[2], double dc[2], double H[4])
+{
+    if (m->kind == OR_FISHEYE) {
+        double k = m->p[0] * 2.0 * m->h * m->h / (m->p[1] * m->p[1]);
+        medium_eval(m, px, py, c, &G[0], &G[1]);
+        dc[0] = G[0];
+        dc[1] = G[1];
+        H[0] = k;
+        H[1] = H[2] = 0.0;
+        H[3] = k;
+        return;
+    }
+    if (m->kind == OR_LINEAR) {
+        medium_eval(m, px, py, c, &G[0], &G[1]);
+        dc[0] = G[0];
+        dc[1] = G[1];
+        H[0] = H[1] = H[2] = H[3] = 0.0;
+        return;
+    }
+    int ix, iy;
+    double t, s;
+    if (!locate(m, px, py, &ix, &iy, &t, &s)) {
+        *c = G[0] = G[1] = dc[0] = dc[1] = NAN;
+        H[0] = H[1] = H[2] = H[3] = NAN;
+        return;
+    }
+    if (m->kind == OR_BSPLINE) {
+        double wx[4], dwx[4], wy[4], dwy[4];
+        double ddwx[4] = {1.0 - t, 3.0 * t - 2.0, 1.0 - 3.0 * t, t};
+        double ddwy[4] = {1.0 - s, 3.0 * s - 2.0, 1.0 - 3.0 * s, s};
+        bspline_w(t, wx, dwx);
+        bspline_w(s, wy, dwy);
+        double v = 0, vx = 0, vy = 0, vxx = 0, vxy = 0, vyy = 0;
+        for (int b = 0; b < 4; b++) {
+            int jy = mirror(iy - 1 + b, m->ny);
+            for (int a = 0; a < 4; a++) {
+                double cf = m->bs[jy * m->nx + mirror(ix - 1 + a, m->nx)];
+                v += cf * wx[a] * wy[b];
+                vx += cf * dwx[a] * wy[b];
+                vy += cf * wx[a] * dwy[b];
+                vxx += cf * ddwx[a] * wy[b];
+                vxy += cf * dwx[a] * dwy[b];
+                vyy += cf * wx[a] * ddwy[b];
+            }
+        }
+        *c = v;
+        G[0] = dc[0] = vx;
+        G[1] = dc[1] = vy;
+        H[0] = vxx;
+        H[1] = H[2] = vxy;
+        H[3] = vyy;
+        return;
+    }
+    /* bilinear: value weights and their t- and s-derivatives, corners
+       (ix,iy), (ix+1,iy), (ix,iy+1), (ix+1,iy+1) */
+    double w[4], wt[4] = {-(1.0 - s), 1.0 - s, -s, s}, ws[4] = {-(1.0 - t), -t, 1.0 - t, t};
+    hat4(t, s, w);
+    int n[4] = {iy * m->nx + ix, iy * m->nx + ix + 1, (iy + 1) * m->nx + ix, (iy + 1) * m->nx + ix + 1};
+    *c = G[0] = G[1] = dc[0] = dc[1] = H[0] = H[1] = H[2] = H[3] = 0.0;
+    for (int k = 0; k < 4; k++) {
+        *c += w[k] * m->c[n[k]];
+        G[0] += w[k] * m->gx[n[k]];
+        G[1] += w[k] * m->gy[n[k]];
+        dc[0] += wt[k] * m->c[n[k]];
+        dc[1] += ws[k] * m->c[n[k]];
+        H[0] += wt[k] * m->gx[n[k]];
+        H[1] += ws[k] * m->gx[n[k]];
+        H[2] += wt[k] * m->gy[n[k]];
+        H[3] += ws[k] * m->gy[n[k]];
+    }
+}
+
+/* y = (x1, x2, d1, d2, dx1, dx2, dd1, dd2) */
+static void rhs8(const Medium *m, const double y[8], double k[8])
+{
+    double c, G[2], dc[2], H[4];
+    medium_eval2(m, y[0], y[1], &c, G, dc, H);
+    const double *d = y + 2, *q = y + 4, *p = y + 6;
+    double gd = G[0] * d[0] + G[1] * d[1];
+    double Hq[2] = {H[0] * q[0] + H[1] * q[1], H[2] * q[0] + H[3] * q[1]};
+    double hqd = Hq[0] * d[0] + Hq[1] * d[1];
+    double dcq = dc[0] * q[0] + dc[1] * q[1];
+    double gp = G[0] * p[0] + G[1] * p[1];
+    k[0] = d[0];
+    k[1] = d[1];
+    for (int a = 0; a < 2; a++) {
+        k[2 + a] = -(G[a] - gd * d[a]) / c;
+        k[4 + a] = p[a];
+        k[6 + a] = -(Hq[a] - hqd * d[a]) / c + (G[a] - gd * d[a]) * dcq / (c * c) + (gp * d[a] + gd * p[a]) / c;
+    }
+}
+
+static void step8(const Medium *m, int integ, double ds, const double y[8], double out[8])
+{
+    double k1[8], k2[8], k3[8], k4[8], tmp[8];
+    if (integ == 2) {
+        rhs8(m, y, k1);
+        for (int i = 0; i < 8; i++) tmp[i] = y[i] + ds * k1[i];
+        rhs8(m, tmp, k2);
+        for (int i = 0; i < 8; i++) out[i] = y[i] + ds / 2.0 * (k1[i] + k2[i]);
+    } else {
+        rhs8(m, y, k1);
+        for (int i = 0; i < 8; i++) tmp[i] = y[i] + ds / 2.0 * k1[i];
+        rhs8(m, tmp, k2);
+        for (int i = 0; i < 8; i++) tmp[i] = y[i] + ds / 2.0 * k2[i];
+        rhs8(m, tmp, k3);
+        for (int i = 0; i < 8; i++) tmp[i] = y[i] + ds * k3[i];
+        rhs8(m, tmp, k4);
+        for (int i = 0; i < 8; i++) out[i] = y[i] + ds / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    }
+    double nrm = sqrt(out[2] * out[2] + out[3] * out[3]);
+    double n0 = out[2] / nrm, n1 = out[3] / nrm;
+    double np = n0 * out[6] + n1 * out[7];
+    out[6] = (out[6] - np * n0) / nrm;
+    out[7] = (out[7] - np * n1) / nrm;
+    out[2] = n0;
+    out[3] = n1;
+}
+
+/* Paraxial quantities of the rays of pairs (e, r) at fixed launch angles:
+     dgdth: derivative of the interception angle (and so of the misfit g) with
+            respect to the launch angle;
+     jac:   ray Jacobian at the interception, u x dx (u the direction of the
+            crossing chord), in metres per radian: the ray-tube width;
+     amp:   sqrt(c(q) / (c(x_e) |jac|)), the 2-D transport-equation amplitude
+            normalised to the point-source far field (1/sqrt(distance) in a
+            homogeneous medium); in 1/sqrt(m);
+     kmah:  number of sign changes of the Jacobian d x dx over the accepted
+            step points and the interception (caustics crossed).
+   The interception point is q = p + t (p' - p) on the crossing chord; its
+   perturbation is dp + t (dp' - dp) + dt (p' - p) with dt keeping |q| = R.
+   status as in or_trace's fixed-angle mode; outputs NaN / -1 off LINKED. */
+int or_paraxial(int kind, int nx, int ny, double h, const double *c, const double *mpar, int n_elem, double radius,
+                double phi0, int integ, double ds_px, int max_steps, int n_pairs, const int32_t *pairs,
+                const double *theta, double *dgdth, double *jac, double *amp, int32_t *kmah, int8_t *status)
+{
+    Medium m;
+    Ring ring;
+    Opts o;
+    if (setup(kind, nx, ny, h, c, mpar, n_elem, radius, phi0, integ, ds_px, 1.0, 1, max_steps, OPT_FIXED, &m, &ring,
+              &o))
+        return -1;
+    const double R = ring.radius_px;
+    for (int i = 0; i < n_pairs; i++) {
+        int e = pairs[2 * i], r = pairs[2 * i + 1];
+        dgdth[i] = jac[i] = amp[i] = NAN;
+        kmah[i] = -1;
+        if (e == r || e < 0 || r < 0 || e >= n_elem || r >= n_elem) {
+            status[i] = ST_BAD_INPUT;
+            continue;
+        }
+        double pe = elem_angle(&ring, e), psi = pe + PI + theta[i];
+        double y[8] = {R * cos(pe), R * sin(pe), cos(psi), sin(psi), 0.0, 0.0, -sin(psi), cos(psi)}, yn[8];
+        double ce, ge[2], dce[2], He[4];
+        medium_eval2(&m, y[0], y[1], &ce, ge, dce, He);
+        int st = ST_NO_HIT, changes = 0;
+        double jprev = 0.0;
+        for (int k = 1; k <= o.max_steps; k++) {
+            double cc, g2[2], d2[2], h4[4];
+            medium_eval2(&m, y[0], y[1], &cc, g2, d2, h4);
+            if (!(cc > 0.0)) {
+                st = ST_BAD_INPUT;
+                break;
+            }
+            step8(&m, o.integ, o.ds, y, yn);
+            if (yn[0] * yn[0] + yn[1] * yn[1] >= R * R) {
+                double ax = yn[0] - y[0], ay = yn[1] - y[1];
+                double A = ax * ax + ay * ay, B = 2.0 * (y[0] * ax + y[1] * ay), C = y[0] * y[0] + y[1] * y[1] - R * R;
+                double D = B * B - 4.0 * A * C;
+                if (D < 0) D = 0;
+                double t = (B >= 0) ? (-2.0 * C) / (B + sqrt(D)) : (-B + sqrt(D)) / (2.0 * A);
+                if (t > 1.0) t = 1.0;
+                if (t < 0.0) t = 0.0;
+                double qx = y[0] + t * ax, qy = y[1] + t * ay;
+                double dqx = y[4] + t * (yn[4] - y[4]), dqy = y[5] + t * (yn[5] - y[5]);
+                double dt = -(qx * dqx + qy * dqy) / (qx * ax + qy * ay);
+                dqx += dt * ax;
+                dqy += dt * ay;
+                double la = sqrt(A), ux = ax / la, uy = ay / la;
+                double jq = ux * dqy - uy * dqx;
+                if (jq * jprev < 0) changes++;
+                double cq, gq[2], dcq[2], hq[4];
+                medium_eval2(&m, qx, qy, &cq, gq, dcq, hq);
+                st = (cq > 0.0) ? ST_LINKED : ST_BAD_INPUT;
+                if (st == ST_LINKED) {
+                    dgdth[i] = (qx * dqy - qy * dqx) / (R * R);
+                    jac[i] = jq * h;
+                    amp[i] = sqrt(cq / (ce * fabs(jq * h)));
+                    kmah[i] = changes;
+                }
+                break;
+            }
+            for (int j = 0; j < 8; j++) y[j] = yn[j];
+            double jn = y[2] * y[5] - y[3] * y[4];
+            if (jn * jprev < 0) changes++;
+            if (jn != 0.0) jprev = jn;
+        }
+        status[i] = (int8_t)st;
+    }
+    teardown(&m);
+    return 0;
+}

@@ -18,8 +18,10 @@ MUTATIONS = {
     "hat_operands_swapped": ("w[1] = t * (1.0 - s);\n    w[2] = (1.0 - t) * s;",
                              "w[1] = (1.0 - t) * s;\n    w[2] = t * (1.0 - s);"),
     "trapezoid_last_weight": ("if (mi == M - 1) return (ds + dsp) / 2.0;", "if (mi == M - 1) return ds;"),
-    "rk4_coefficient": ("2.0 * k3[i] + k4[i]", "k3[i] + k4[i]"),
-    "heun_combination": ("out[i] = y[i] + ds / 2.0 * (k1[i] + k2[i]);", "out[i] = y[i] + ds * k2[i];"),
+    "rk4_coefficient": ("i < 4; i++) out[i] = y[i] + ds / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);",
+                        "i < 4; i++) out[i] = y[i] + ds / 6.0 * (k1[i] + 2.0 * k2[i] + k3[i] + k4[i]);"),
+    "heun_combination": ("i < 4; i++) out[i] = y[i] + ds / 2.0 * (k1[i] + k2[i]);",
+                         "i < 4; i++) out[i] = y[i] + ds * k2[i];"),
     "misfit_sign": ("return mod2pi(atan2(qy, qx) - pe) - mod2pi(pr - pe);",
                     "return mod2pi(pr - pe) - mod2pi(atan2(qy, qx) - pe);"),
     "straight_angle_offset": ("return (mod2pi(elem_angle(ring, rcv) - elem_angle(ring, e)) - PI) / 2.0;",
@@ -50,6 +52,13 @@ MUTATIONS = {
     "sart_sequential_update": ("for (int64_t k = rowptr[i]; k < rowptr[i + 1]; k++) upd[col[k]] += val[k] * r;",
                                "for (int64_t k = rowptr[i]; k < rowptr[i + 1]; k++) x[col[k]] += lambda * val[k] * r "
                                "/ V[col[k]];"),
+    "paraxial_dKdd_sign": ("+ (gp * d[a] + gd * p[a]) / c;", "- (gp * d[a] + gd * p[a]) / c;"),
+    "paraxial_dc_term_dropped": (" + (G[a] - gd * d[a]) * dcq / (c * c)", ""),
+    "paraxial_start_perturbation": ("0.0, 0.0, -sin(psi), cos(psi)}, yn[8];", "0.0, 0.0, sin(psi), -cos(psi)}, yn[8];"),
+    "paraxial_hit_shift_dropped": ("dqx += dt * ax;", "dqx += 0.0 * ax;"),
+    "paraxial_bspline_curvature_weight": ("double ddwx[4] = {1.0 - t, 3.0 * t - 2.0, 1.0 - 3.0 * t, t};",
+                                          "double ddwx[4] = {1.0 - t, 3.0 * t - 2.0, 1.0 - 3.0 * t, -t};"),
+    "paraxial_bilinear_hessian_operand": ("H[1] += ws[k] * m->gx[n[k]];", "H[1] += wt[k] * m->gx[n[k]];"),
     "fan_target_wrong_receiver": ("G[j - 1] = row[j - 1].st == ST_LINKED ? (row[j - 1].g + Dj) - Dr : NAN;",
                                   "G[j - 1] = row[j - 1].st == ST_LINKED ? row[j - 1].g - Dr : NAN;"),
 }
@@ -78,6 +87,10 @@ PINS = [
     lambda o: P.test_fan_cubic_falls_back(o),
     lambda o: P.test_fan_start_same_roots_fewer_rays(o),
     lambda o: P.test_fan_start_fisheye_reversed_orientation(o),
+    lambda o: P.test_paraxial_homogeneous_closed_form(o, "rk4"),
+    lambda o: P.test_paraxial_matches_finite_differences(o, "bspline", 1e-7),
+    lambda o: P.test_paraxial_matches_finite_differences(o, "bilinear", 2e-5),
+    lambda o: P.test_paraxial_fisheye_focus(o),
     lambda o: P.test_sart_one_row_is_exact(o),
     lambda o: P.test_sart_step_is_preconditioned_gradient_step(o),
     lambda o: P.test_sart_consistent_system_converges(o),

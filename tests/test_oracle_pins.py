@@ -635,3 +635,90 @@ def test_sart_zero_rows_and_columns_take_no_part(orc):
     ref = orc.sart(*_csr(W), b, np.zeros(9), 5, 1.3)
     assert x[3] == 7.0
     np.testing.assert_allclose(np.delete(x, 3), ref, rtol=1e-14)
+
+
+# ------------------------------------------------------------ paraxial ------
+@pytest.mark.parametrize("integ", ["rk4", "heun"])
+def test_paraxial_homogeneous_closed_form(orc, integ):
+    """Straight rays: the chord at launch angle theta (from the inward normal)
+    has length L = 2 R cos(theta) and subtends a central angle pi + 2 theta, so
+    dg/dtheta = 2, the ray-tube width per radian is L, the 2-D amplitude
+    1/sqrt(L), and no caustic is crossed."""
+    n, h, R = 64, 1e-3, 0.025
+    med = orc.grid_medium(np.full((n, n), 1500.0), h)
+    rng = np.random.default_rng(81)
+    th = rng.uniform(-1.2, 1.2, 30)
+    pairs = np.tile(np.array([[3, 9]], np.int32), (30, 1))
+    p = orc.paraxial(med, (16, R, 0.2), pairs, th, integ=integ)
+    L = 2 * R * np.cos(th)
+    assert np.all(p["status"] == orc.LINKED)
+    np.testing.assert_allclose(p["dgdth"], 2.0, rtol=1e-10)
+    np.testing.assert_allclose(p["jac"], L, rtol=1e-10)
+    np.testing.assert_allclose(p["amp"], 1 / np.sqrt(L), rtol=1e-10)
+    assert np.all(p["kmah"] == 0)
+
+
+def _fd_hit(orc, med, ring, pairs, th, eps):
+    """Central differences of the misfit and of the interception point."""
+    out = []
+    for sgn in (1, -1):
+        g, q = [], []
+        for (e, r), t in zip(pairs, th + sgn * eps):
+            pts, _, gg = orc.march_points(med, ring, int(e), int(r), float(t))
+            g.append(gg)
+            q.append(pts[-1])
+        out.append((np.array(g), np.array(q)))
+    return (out[0][0] - out[1][0]) / (2 * eps), (out[0][1] - out[1][1]) / (2 * eps)
+
+
+@pytest.mark.parametrize("interp,tol", [("bspline", 1e-7), ("bilinear", 2e-5)])
+def test_paraxial_matches_finite_differences(orc, interp, tol):
+    """The paraxial system is the derivative of the traced ray with respect to
+    its launch angle: dg/dtheta and the Jacobian (the interception point's
+    displacement across the ray) against central differences of the march on
+    a Gaussian-inclusion medium.  The C2 B-spline field gives a smooth map; the
+    bilinear field's gradient derivative jumps between cells, hence the looser
+    bound."""
+    n, h = 96, 0.5e-3
+    c = synth.gaussian_inclusions(n, n, h, seed=21, r_max=0.7 * 0.45 * n * h)
+    ring = (24, 0.45 * n * h * 0.9, 0.1)
+    pairs = synth.all_pairs(24)[::11]
+    med = orc.grid_medium(c, h, interp=interp)
+    th = orc.trace(med, ring, pairs)["theta"]
+    p = orc.paraxial(med, ring, pairs, th)
+    dg, dq = _fd_hit(orc, med, ring, pairs, th, 1e-6)
+    assert np.abs(p["dgdth"] / dg - 1).max() < tol
+    # the Jacobian: displacement of the interception across the crossing chord
+    u = []
+    for (e, r), t in zip(pairs, th):
+        pts, _, _ = orc.march_points(med, ring, int(e), int(r), float(t))
+        d = pts[-1] - pts[-2]
+        u.append(d / np.linalg.norm(d))
+    u = np.array(u)
+    jac_fd = (u[:, 0] * dq[:, 1] - u[:, 1] * dq[:, 0]) * h
+    assert np.abs(p["jac"] / jac_fd - 1).max() < 10 * tol
+
+
+def test_paraxial_fisheye_focus(orc):
+    """Maxwell's fish-eye images a point on the unit circle perfectly onto its
+    antipode (Section 4): rays from [0, a] within +-pi/3 all meet [0, -a], so
+    there the misfit no longer depends on the launch angle and the ray tube has
+    no width (both to the discretisation error at ds/dx = 1, against dg/dtheta
+    = 2 and widths ~a of an unfocused fan).  A ring of radius 2a puts the
+    conjugate point [0, -a/2] inside: every ray crosses that one focus."""
+    g = _golden()
+    a, dx = g["a"], g["dx_over_a"] * g["a"]
+    th = np.linspace(*g["al_theta_range"], 21)
+    pairs = np.tile(np.array([[0, 2]], np.int32), (len(th), 1))
+    for R_ring in (a, 2 * a):
+        n = 2 * int(math.ceil(1.1 * R_ring / dx)) + 1
+        med = {"kind": "fisheye", "nx": n, "ny": n, "h": dx, "c0": 1.0, "R": a}
+        for integ in ("rk4", "heun"):
+            p = orc.paraxial(med, (4, R_ring, math.pi / 2), pairs, th, integ=integ, ds_px=1.0)
+            assert np.all(p["status"] == orc.LINKED)
+            if R_ring == a:
+                assert np.abs(p["dgdth"]).max() < 0.01
+                assert np.abs(p["jac"]).max() < 0.005 * a
+            else:
+                assert np.all(p["kmah"] == 1)
+                assert np.abs(p["jac"]).min() > 0.1 * a
