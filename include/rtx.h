@@ -195,6 +195,32 @@ int rtx_tof_forward(rtx_plan plan, const double *c, const int32_t *pairs, int64_
 int rtx_sart(rtx_plan plan, int64_t n_rows, int64_t nnz, const int64_t *w_rowptr, const int32_t *w_col,
              const void *w_val, const double *b, double *x, int32_t n_iter, double lambda, void *stream);
 
+/* Paraxial ray (Sec. 3.5: the default way to the ray Jacobian that the
+   geometric spreading of the ray-Born Green's functions needs) along the rays
+   traced at the given launch angles, typically the linked ones.  The
+   first-order perturbation (dx, dd) of position and direction per unit change
+   of the launch angle is integrated with the ray by the same Runge-Kutta
+   scheme (the standard variational equations of the ray equations of Sec. 3.2;
+   the paper cites them only).  Per pair (each output may be NULL except status):
+     dgdth  [n] float64: derivative of the interception angle, and so of the
+                misfit g, with respect to the launch angle
+     jac    [n] float64: ray Jacobian at the interception, u x dx with u the
+                direction of the crossing step, metres per radian (the width
+                of the ray tube; its sign flips at each caustic)
+     amp    [n] float64: geometric-spreading amplitude sqrt(c(x_r) /
+                (c(x_e) |jac|)), 1/sqrt(m): the 2-D transport-equation solution
+                normalised to the point-source far field (1/sqrt(distance) in a
+                homogeneous medium)
+     kmah   [n] int32: sign changes of the Jacobian along the ray (caustics)
+     status [n] int8: rtx_ray_status of the traced ray; outputs are NaN / -1
+                unless LINKED
+   theta [n] float64 launch angles (as rtx_trace_rays); pairs and c as in
+   rtx_trace_rays; the plan's precision, integrator, step, step limit and
+   interpolation apply.  Errors as rtx_trace_rays (RTX_E_ARG, nothing
+   enqueued). */
+int rtx_paraxial(rtx_plan plan, const double *c, const int32_t *pairs, int64_t n_pairs, const double *theta,
+                 double *dgdth, double *jac, double *amp, int32_t *kmah, int8_t *status, void *stream);
+
 /* Free march without a ring: the ray equations of Sec. 3.2 followed for a
    fixed number of steps, as in the trajectory (radius) experiment of Sec. 4.1.
      x0   [n_rays][2] float64, device: start points, metres from the grid centre

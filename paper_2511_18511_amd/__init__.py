@@ -136,6 +136,23 @@ class Plan:
         B.rtx_march_free(self._handle, _ptr(c), n, _ptr(x0), _ptr(d0), int(n_steps), _ptr(pts), _stream())
         return pts
 
+    def paraxial(self, theta, pairs=None, c=None, **over):
+        """Paraxial ray along the rays at the given launch angles (Sec. 3.5):
+        dict of device tensors dgdth, jac (m/rad), amp (1/sqrt(m)), kmah
+        (int32) and status."""
+        if c is not None:
+            _dev_check(c, torch.float64, (self.ny, self.nx), "c")
+        pairs, n = self._pairs(pairs)
+        _dev_check(theta, torch.float64, (n,), "theta")
+        dev = theta.device
+        out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("dgdth", "jac", "amp")}
+        out["kmah"] = torch.empty(n, dtype=torch.int32, device=dev)
+        out["status"] = torch.empty(n, dtype=torch.int8, device=dev)
+        self._apply(0, **over)
+        B.rtx_paraxial(self._handle, _ptr(c), _ptr(pairs), n, _ptr(theta), _ptr(out["dgdth"]), _ptr(out["jac"]),
+                       _ptr(out["amp"]), _ptr(out["kmah"]), _ptr(out["status"]), _stream())
+        return out
+
     def sart(self, w_rowptr, w_col, w_val, b, x=None, n_iter=10, lam=1.0):
         """SART iterations (Sec. 3.1) on W x = b with W as returned by
         weights()/trace(weights=True); x (float64 [ny, nx] device, updated in

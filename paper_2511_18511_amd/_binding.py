@@ -18,7 +18,7 @@ RTX_RAY_LINKED, RTX_RAY_NOT_CONVERGED, RTX_RAY_NO_HIT, RTX_RAY_BAD_INPUT = 0, 1,
 
 # every symbol include/rtx.h declares
 EXPORTS = ("rtx_plan_create", "rtx_plan_destroy", "rtx_plan_set_opts", "rtx_set_medium", "rtx_trace_rays",
-           "rtx_tof_forward", "rtx_march_free", "rtx_sart", "rtx_tof_adjoint", "rtx_plan_stats", "rtx_plan_region_stats", "rtx_plan_timing",
+           "rtx_tof_forward", "rtx_march_free", "rtx_paraxial", "rtx_sart", "rtx_tof_adjoint", "rtx_plan_stats", "rtx_plan_region_stats", "rtx_plan_timing",
            "rtx_plan_timings", "rtx_plan_set_launch", "rtx_batch_create",
            "rtx_batch_run", "rtx_batch_times", "rtx_batch_destroy", "rtx_last_error")
 
@@ -69,6 +69,7 @@ def load():
     L.rtx_trace_rays.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
     L.rtx_tof_forward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
     L.rtx_march_free.argtypes = [vp, vp, i64, vp, vp, C.c_int32, vp, vp]
+    L.rtx_paraxial.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
     L.rtx_sart.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, C.c_int32, C.c_double, vp]
     L.rtx_tof_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(C.c_double), i32, i32, vp, vp]
     L.rtx_plan_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
@@ -123,6 +124,10 @@ def rtx_tof_forward(plan, c, pairs, n_pairs, theta, tof, status, stream):
 
 def rtx_march_free(plan, c, n_rays, x0, d0, n_steps, pts, stream):
     return check(load().rtx_march_free(plan, c, int(n_rays), x0, d0, int(n_steps), pts, stream))
+
+
+def rtx_paraxial(plan, c, pairs, n_pairs, theta, dgdth, jac, amp, kmah, status, stream):
+    return check(load().rtx_paraxial(plan, c, pairs, int(n_pairs), theta, dgdth, jac, amp, kmah, status, stream))
 
 
 def rtx_sart(plan, n_rows, nnz, w_rowptr, w_col, w_val, b, x, n_iter, lam, stream):

@@ -593,6 +593,11 @@ struct LookupSampler {
     __device__ __forceinline__ void done(int) {}
 };
 
+// The new state from a step's stage results: compensated (COMP) or plain
+// position and direction update, then the direction renormalised.
+template <class R, bool COMP>
+__device__ __forceinline__ StepOut<R> advance(const Ray<R> &y, const StageOut<R> &st, Ray<R> &nxt);
+
 template <class R, bool COMP, int INTEG, bool BSP = false>
 __device__ __forceinline__ StepOut<R> ray_step(const Medium<R> &M, Slot<R> (&C)[3], const Ray<R> &y, Ray<R> &nxt,
                                                R ds)
@@ -609,6 +614,12 @@ __device__ __forceinline__ StepOut<R> ray_step(const Medium<R> &M, Slot<R> (&C)[
             stages<R, INTEG>(ls, y, ds, st);
         }
     }
+    return advance<R, COMP>(y, st, nxt);
+}
+
+template <class R, bool COMP>
+__device__ __forceinline__ StepOut<R> advance(const Ray<R> &y, const StageOut<R> &st, Ray<R> &nxt)
+{
     StepOut<R> o;
     o.s1 = st.s1;
     o.ic1 = st.ic1;
@@ -1869,6 +1880,236 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
+// ----------------------------------------------------------- paraxial ray --
+// The paraxial ray of Sec. 3.5 (the default way to the ray Jacobian): the
+// first-order perturbation (q, p) = (dx, dd) of a ray's position and direction
+// caused by a perturbation of its launch angle, from the variational equations
+// of the ray ODE x' = d, d' = K(x, d) = -(G - (G.d) d) / c:
+//   q' = p,   p' = dK = (((H q).d + G.p) d - H q + (G.d) p) / c - K (grad c . q) / c,
+// with grad c the gradient of the interpolated c and H = dG/dx the derivative
+// of the interpolated G.  The reference ray is advanced by the tracer's own
+// stage arithmetic (so it is the traced ray), the perturbation by the same
+// Runge-Kutta stages on the tangent-linear system, and the renormalisation of
+// d is linearised.  One lane per ray, direct lookups.
+template <class R>
+struct SampleP {
+    Sample<R> b;              // c, G and the cell, as the tracer sees them
+    R cx, cy;                 // gradient of the interpolated c
+    R hxx, hxy, hyx, hyy;     // dG_x/dx, dG_x/dy, dG_y/dx, dG_y/dy
+};
+
+template <class R>
+__device__ __forceinline__ SampleP<R> lookup_para(const Medium<R> &M, R uh, R du, R vh, R dv)
+{
+    SampleP<R> o;
+    o.b.ix = min(max((int)(uh + du), 0), M.nx - 2);
+    o.b.iy = min(max((int)(vh + dv), 0), M.ny - 2);
+    o.b.t = fmin_(fmax_((uh - (R)o.b.ix) + du, (R)0), (R)1);
+    o.b.s = fmin_(fmax_((vh - (R)o.b.iy) + dv, (R)0), (R)1);
+    R v[12];
+    load_cell(M.tab, __umul24((uint32_t)o.b.iy, (uint32_t)(M.nx - 1)) + (uint32_t)o.b.ix, v);
+    interp(v, o.b.t, o.b.s, o.b);
+    const R t = o.b.t, s = o.b.s;  // f = a + b t + c s + d t s per field
+    o.cx = fma(s, v[3], v[1]);
+    o.cy = fma(t, v[3], v[2]);
+    o.hxx = fma(s, v[7], v[5]);
+    o.hxy = fma(t, v[7], v[6]);
+    o.hyx = fma(s, v[11], v[9]);
+    o.hyy = fma(t, v[11], v[10]);
+    return o;
+}
+
+template <class R>
+__device__ __forceinline__ SampleP<R> lookup_para_bsp(const Medium<R> &M, R uh, R du, R vh, R dv)
+{
+    SampleP<R> o;
+    o.b = lookup_bsp(M, uh, du, vh, dv);
+    R q[16], wx[4], dwx[4], wy[4], dwy[4];
+    load_stencil(M.tab, __umul24((uint32_t)o.b.iy, (uint32_t)(M.nx - 1)) + (uint32_t)o.b.ix, q);
+    bsp_weights(o.b.t, wx, dwx);
+    bsp_weights(o.b.s, wy, dwy);
+    const R t = o.b.t, s = o.b.s;  // second derivatives of the cubic's weights
+    const R ddx[4] = {(R)1 - t, fma((R)3, t, (R)-2), fma((R)-3, t, (R)1), t};
+    const R ddy[4] = {(R)1 - s, fma((R)3, s, (R)-2), fma((R)-3, s, (R)1), s};
+    R cxx = 0, cxy = 0, cyy = 0;
+    for (int b = 0; b < 4; b++) {
+        R rxx = 0, rx = 0, r = 0;
+        for (int a = 0; a < 4; a++) {
+            rxx = fma(q[4 * b + a], ddx[a], rxx);
+            rx = fma(q[4 * b + a], dwx[a], rx);
+            r = fma(q[4 * b + a], wx[a], r);
+        }
+        cxx = fma(rxx, wy[b], cxx);
+        cxy = fma(rx, dwy[b], cxy);
+        cyy = fma(r, ddy[b], cyy);
+    }
+    o.cx = o.b.gx;
+    o.cy = o.b.gy;
+    o.hxx = cxx;
+    o.hxy = o.hyx = cxy;
+    o.hyy = cyy;
+    return o;
+}
+
+// Records the extended sample of every stage for the tangent-linear pass.
+template <class R, bool BSP>
+struct ParaSampler {
+    const Medium<R> &M;
+    R uh, vh;
+    SampleP<R> s[4];
+    __device__ __forceinline__ Sample<R> get(int k, R du, R dv)
+    {
+        s[k] = BSP ? lookup_para_bsp(M, uh, du, vh, dv) : lookup_para(M, uh, du, vh, dv);
+        return s[k].b;
+    }
+    __device__ __forceinline__ void done(int) {}
+};
+
+// dK at a stage with direction d and curvature k, perturbation (q, p).
+template <class R>
+__device__ __forceinline__ void dcurv(const SampleP<R> &S, R ic, R dx, R dy, R kx, R ky, R qx, R qy, R px, R py,
+                                      R &ox, R &oy)
+{
+    const R hqx = fma(S.hxy, qy, S.hxx * qx), hqy = fma(S.hyy, qy, S.hyx * qx);
+    const R a = fma(hqy, dy, hqx * dx) + fma(S.b.gy, py, S.b.gx * px);  // (H q).d + G.p
+    const R gd = fma(S.b.gy, dy, S.b.gx * dx), dcq = ic * fma(S.cy, qy, S.cx * qx);
+    ox = fma(-kx, dcq, ic * (fma(a, dx, gd * px) - hqx));
+    oy = fma(-ky, dcq, ic * (fma(a, dy, gd * py) - hqy));
+}
+
+// Tangent-linear Runge-Kutta step of (q, p) along the step the sampler recorded
+// (the stage directions and curvatures are recomputed as the tracer's stages
+// computed them).
+template <class R, int INTEG, bool BSP>
+__device__ __forceinline__ void para_tangent(const ParaSampler<R, BSP> &P, const Ray<R> &y, R ds, R &qx, R &qy,
+                                             R &px, R &py)
+{
+    const R d1x = y.dxh + y.dxl, d1y = y.dyh + y.dyl;
+    R ic, k1x, k1y, k2x, k2y, e1x, e1y, e2x, e2y;
+    ic = rcp(P.s[0].b.c);
+    curvature(P.s[0].b, ic, d1x, d1y, k1x, k1y);
+    dcurv(P.s[0], ic, d1x, d1y, k1x, k1y, qx, qy, px, py, e1x, e1y);
+    if (INTEG == 4) {
+        const R h2 = ds * (R)0.5;
+        R k3x, k3y, k4x, k4y, e3x, e3y, e4x, e4y;
+        const R d2x = fma(h2, k1x, d1x), d2y = fma(h2, k1y, d1y);
+        const R q2x = fma(h2, px, qx), q2y = fma(h2, py, qy), p2x = fma(h2, e1x, px), p2y = fma(h2, e1y, py);
+        ic = rcp(P.s[1].b.c);
+        curvature(P.s[1].b, ic, d2x, d2y, k2x, k2y);
+        dcurv(P.s[1], ic, d2x, d2y, k2x, k2y, q2x, q2y, p2x, p2y, e2x, e2y);
+        const R d3x = fma(h2, k2x, d1x), d3y = fma(h2, k2y, d1y);
+        const R q3x = fma(h2, p2x, qx), q3y = fma(h2, p2y, qy), p3x = fma(h2, e2x, px), p3y = fma(h2, e2y, py);
+        ic = rcp(P.s[2].b.c);
+        curvature(P.s[2].b, ic, d3x, d3y, k3x, k3y);
+        dcurv(P.s[2], ic, d3x, d3y, k3x, k3y, q3x, q3y, p3x, p3y, e3x, e3y);
+        const R d4x = fma(ds, k3x, d1x), d4y = fma(ds, k3y, d1y);
+        const R q4x = fma(ds, p3x, qx), q4y = fma(ds, p3y, qy), p4x = fma(ds, e3x, px), p4y = fma(ds, e3y, py);
+        ic = rcp(P.s[3].b.c);
+        curvature(P.s[3].b, ic, d4x, d4y, k4x, k4y);
+        dcurv(P.s[3], ic, d4x, d4y, k4x, k4y, q4x, q4y, p4x, p4y, e4x, e4y);
+        const R s6 = ds * (R)(1.0 / 6.0);
+        qx = fma(s6, px + (R)2 * (p2x + p3x) + p4x, qx);
+        qy = fma(s6, py + (R)2 * (p2y + p3y) + p4y, qy);
+        px = fma(s6, e1x + (R)2 * (e2x + e3x) + e4x, px);
+        py = fma(s6, e1y + (R)2 * (e2y + e3y) + e4y, py);
+    } else {
+        const R d2x = fma(ds, k1x, d1x), d2y = fma(ds, k1y, d1y);
+        const R q2x = fma(ds, px, qx), q2y = fma(ds, py, qy), p2x = fma(ds, e1x, px), p2y = fma(ds, e1y, py);
+        ic = rcp(P.s[3].b.c);
+        curvature(P.s[3].b, ic, d2x, d2y, k2x, k2y);
+        dcurv(P.s[3], ic, d2x, d2y, k2x, k2y, q2x, q2y, p2x, p2y, e2x, e2y);
+        const R s2 = ds * (R)0.5;
+        qx = fma(s2, px + p2x, qx);
+        qy = fma(s2, py + p2y, qy);
+        px = fma(s2, e1x + e2x, px);
+        py = fma(s2, e1y + e2y, py);
+    }
+}
+
+template <class R, bool COMP, int INTEG, bool BSP>
+__global__ void __launch_bounds__(kBlock)
+    k_paraxial(Medium<R> M, Geo g, const int32_t *__restrict__ pairs, int64_t n, const double *__restrict__ theta,
+               int max_steps, double *__restrict__ dgdth, double *__restrict__ jac, double *__restrict__ amp,
+               int32_t *__restrict__ kmah, int8_t *__restrict__ status)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int e, r;
+    TraceArgs pa;
+    pa.pairs = pairs;
+    double o_dg = NAN, o_j = NAN, o_a = NAN;
+    int o_k = -1, st = RTX_RAY_BAD_INPUT;
+    if (pair_of(pa, g, i, e, r)) {
+        const Emitter em = emitter_of(g, e);
+        Ray<R> ray;
+        start_ray<R, COMP>(ray, g, em, theta[i]);
+        double sp, cp;
+        sincos(em.pe + kPi + theta[i], &sp, &cp);
+        R qx = (R)0, qy = (R)0, px = (R)(-sp), py = (R)cp;  // d(direction)/d(theta)
+        const R ds = (R)g.ds, R2 = (R)(g.R * g.R), cxr = (R)g.cx, cyr = (R)g.cy;
+        const double ce = (double)lookup_at<R, COMP, BSP>(M, g, em.ex, em.ey).c;
+        R jprev = (R)0;
+        int changes = 0;
+        st = RTX_RAY_NO_HIT;
+        for (int m = 0; m < max_steps; m++) {
+            ParaSampler<R, BSP> P{M, ray.uh, ray.vh};
+            StageOut<R> so;
+            stages<R, INTEG>(P, ray, ds, so);
+            if (!(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh)) {
+                st = RTX_RAY_BAD_INPUT;
+                break;
+            }
+            R nqx = qx, nqy = qy, npx = px, npy = py;
+            para_tangent<R, INTEG, BSP>(P, ray, ds, nqx, nqy, npx, npy);
+            Ray<R> nxt;
+            (void)advance<R, COMP>(ray, so, nxt);
+            {  // linearised renormalisation: p <- (p - (n.p) n) / |d| of the unnormalised d
+                const R ux = (ray.dxh + ray.dxl) + so.idx, uy = (ray.dyh + ray.dyl) + so.idy;
+                const R nrm = sqrt(ux * ux + uy * uy), nx = ux / nrm, ny = uy / nrm;
+                const R np = fma(ny, npy, nx * npx);
+                npx = (npx - np * nx) / nrm;
+                npy = (npy - np * ny) / nrm;
+            }
+            const R pu = (nxt.uh - cxr) + nxt.ul, pv = (nxt.vh - cyr) + nxt.vl;
+            if (pu * pu + pv * pv >= R2) {
+                const Hit hit = intersect<R>(g, ray, nxt);
+                const double ax = (((double)nxt.uh - g.cx) + (double)nxt.ul) - (((double)ray.uh - g.cx) + (double)ray.ul);
+                const double ay = (((double)nxt.vh - g.cy) + (double)nxt.vl) - (((double)ray.vh - g.cy) + (double)ray.vl);
+                double dqx = (double)qx + hit.t * ((double)nqx - (double)qx);
+                double dqy = (double)qy + hit.t * ((double)nqy - (double)qy);
+                const double dt = -(hit.qx * dqx + hit.qy * dqy) / (hit.qx * ax + hit.qy * ay);
+                dqx += dt * ax;
+                dqy += dt * ay;
+                const double la = sqrt(ax * ax + ay * ay);
+                const double jq = (ax / la) * dqy - (ay / la) * dqx;
+                if (jq * (double)jprev < 0) changes++;
+                const double cq = (double)lookup_at<R, COMP, BSP>(M, g, hit.qx, hit.qy).c;
+                st = cq > 0.0 ? RTX_RAY_LINKED : RTX_RAY_BAD_INPUT;
+                if (st == RTX_RAY_LINKED) {
+                    o_dg = (hit.qx * dqy - hit.qy * dqx) / (g.R * g.R);
+                    o_j = jq * g.h;
+                    o_a = sqrt(cq / (ce * fabs(o_j)));
+                    o_k = changes;
+                }
+                break;
+            }
+            const R jn = (nxt.dxh + nxt.dxl) * nqy - (nxt.dyh + nxt.dyl) * nqx;
+            if (jn * jprev < (R)0) changes++;
+            if (jn != (R)0) jprev = jn;
+            ray = nxt;
+            qx = nqx;
+            qy = nqy;
+            px = npx;
+            py = npy;
+        }
+    }
+    if (dgdth) dgdth[i] = o_dg;
+    if (jac) jac[i] = o_j;
+    if (amp) amp[i] = o_a;
+    if (kmah) kmah[i] = o_k;
+    status[i] = (int8_t)st;
+}
+
 // ------------------------------------------------------------------- SART --
 // SART on the system matrix W (Sec. 3.1's default solver of the linearised ToF
 // subproblem).  Every step streams W with one wave per row (CSR) or per column
@@ -2512,6 +2753,21 @@ int batch_upload(rtx_batch_s *Bt)
 
 // ====================================================================== ABI ==
 template <class R, bool COMP>
+int launch_paraxial(rtx_plan_s *P, const int32_t *pairs, int64_t n, const double *theta, double *dgdth, double *jac,
+                    double *amp, int32_t *kmah, int8_t *status, hipStream_t s)
+{
+    Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
+    Geo g = make_geo(P);
+    auto kern = P->bsp ? (P->opts.integ == RTX_RK4 ? k_paraxial<R, COMP, 4, true> : k_paraxial<R, COMP, 2, true>)
+                       : (P->opts.integ == RTX_RK4 ? k_paraxial<R, COMP, 4, false> : k_paraxial<R, COMP, 2, false>);
+    const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, M, g, pairs, n, theta, max_steps_of(P), dgdth, jac,
+                       amp, kmah, status);
+    HIP_TRY(hipGetLastError());
+    return RTX_OK;
+}
+
+template <class R, bool COMP>
 int launch_march(rtx_plan_s *P, int64_t n_rays, const double *x0, const double *d0, int n_steps, double *pts,
                  hipStream_t s)
 {
@@ -2735,6 +2991,22 @@ int rtx_sart(rtx_plan P, int64_t n_rows, int64_t nnz, const int64_t *w_rowptr, c
     if (P->opts.prec == RTX_F32C)
         return launch_sart<float>(P, n_rows, nnz, w_rowptr, w_col, (const float *)w_val, b, x, n_iter, lambda, s);
     return launch_sart<double>(P, n_rows, nnz, w_rowptr, w_col, (const double *)w_val, b, x, n_iter, lambda, s);
+}
+
+int rtx_paraxial(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_pairs, const double *theta,
+                 double *dgdth, double *jac, double *amp, int32_t *kmah, int8_t *status, void *stream)
+{
+    g_last_error.clear();
+    if (!P) return fail(RTX_E_ARG, "null plan");
+    int rc = check_pairs(P, pairs, n_pairs);
+    if (rc) return rc;
+    if (n_pairs > 0 && (!theta || !status)) return fail(RTX_E_ARG, "theta and status are required");
+    hipStream_t s = (hipStream_t)stream;
+    rc = pack(P, c, s);
+    if (rc || n_pairs == 0) return rc;
+    if (P->opts.prec == RTX_F32C)
+        return launch_paraxial<float, true>(P, pairs, n_pairs, theta, dgdth, jac, amp, kmah, status, s);
+    return launch_paraxial<double, false>(P, pairs, n_pairs, theta, dgdth, jac, amp, kmah, status, s);
 }
 
 int rtx_march_free(rtx_plan P, const double *c, int64_t n_rays, const double *x0, const double *d0,
