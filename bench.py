@@ -191,7 +191,7 @@ def measured_traffic(_unused=None):
         if d.get("source_sha256") != sha:
             continue
         for name, v in d.get("kernels", {}).items():
-            if name.startswith("k_trace<float, true, 4, false, true>"):  # the fan-seeded linking pass
+            if name.startswith("k_trace<float, true, 4, false, true, false>"):  # the fan-seeded linking pass
                 return v["fetch_bytes"] + v["write_bytes"]
     return None
 
