@@ -19,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle_rt.c")
+_SRC3 = os.path.join(_HERE, "oracle_rt3.c")
 _LIB = os.path.join(_HERE, "liboracle_rt.so")
 
 LINKED, NOT_CONVERGED, NO_HIT, BAD_INPUT = 0, 1, 2, 3
@@ -27,13 +28,15 @@ HEUN, RK4 = 2, 4
 LENGTH, DTDC = 0, 1
 
 
-def build(force=True, src=_SRC, out=_LIB):
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
-    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
+def build(force=True, src=_SRC, out=_LIB, src3=_SRC3):
+    """Compile the oracle (2-D and 3-D sources) with gcc (no fast-math, no FMA
+    contraction)."""
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= max(os.path.getmtime(src),
+                                                                          os.path.getmtime(src3)):
         return out
     tmp = out + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-                           "-o", tmp, src, "-lm"])
+                           "-o", tmp, src, src3, "-lm"])
     os.replace(tmp, out)
     return out
 
@@ -72,6 +75,13 @@ def _load(path):
     L.or_rayborn_rho.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
     L.or_paraxial.argtypes = med + [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int, C.c_int, _ip,
                                      _dp, _dp, _dp, _dp, _ip, _bp]
+    med3 = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _dp, _dp]
+    L.or3_trace.argtypes = med3 + [C.c_int, _dp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                   C.c_int, _ip, _dp, _dp, _dp, _dp, _ip, _bp]
+    L.or3_march_free.argtypes = med3 + [C.c_int, C.c_double, _dp, _dp, C.c_int, _dp]
+    L.or3_jac0.argtypes = [C.c_int, _dp, C.c_double, C.c_int, C.c_int, _dp, _dp, _dp]
+    L.or3_interp.argtypes = med3 + [C.c_int, _dp, _dp, _dp]
+    L.or3_misfit.argtypes = med3 + [C.c_int, _dp, C.c_int, C.c_double, C.c_int, C.c_int, _dp, _dp, _dp]
     L.or_sart.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int64), _ip, _dp, _dp, _dp, C.c_int, C.c_double]
     _lib = L
 
@@ -312,3 +322,92 @@ def paraxial(medium, ring, pairs, theta, integ="rk4", ds_px=0.25, max_steps=0):
     if rc:
         raise ValueError("bad medium")
     return out
+
+
+# ------------------------------------------------------------------- 3-D ----
+# Volumes: {"kind": "grid", "c": float64[nz, ny, nx], "h": h} (trilinear),
+# {"kind": "fisheye", "n": (nx, ny, nz), "h": h, "c0": c0, "R": R} or
+# {"kind": "linear", "n": (nx, ny, nz), "h": h, "c0": c0, "a": (ax, ay, az)}.
+def _medium3_args(medium):
+    kind, h = medium["kind"], float(medium["h"])
+    if kind == "grid":
+        c = np.ascontiguousarray(medium["c"], dtype=np.float64)
+        nz, ny, nx = c.shape
+        return [0, nx, ny, nz, h, _d(c), None], (c,)
+    par = np.zeros(4)
+    if kind == "fisheye":
+        par[:2] = (medium["c0"], medium["R"])
+        code = 1
+    elif kind == "linear":
+        par[0] = medium["c0"]
+        par[1:4] = medium["a"]
+        code = 2
+    else:
+        raise ValueError(kind)
+    nx, ny, nz = medium.get("n", (8, 8, 8))
+    return [code, int(nx), int(ny), int(nz), h, None, _d(par)], (par,)
+
+
+def trace3(medium, elem, pairs, u=None, integ="rk4", ds_px=0.25, tol_px=1e-3, max_marches=30, max_steps=0,
+           warm=False, fixed=False):
+    """3-D tracing between elements elem [n][3] (metres from the grid centre,
+    on one sphere): dict of u [n, 2], tof, len, miss_px, n_marches, status."""
+    args, keep = _medium3_args(medium)
+    elem = np.ascontiguousarray(elem, dtype=np.float64)
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    n = pairs.shape[0]
+    uu = np.zeros((n, 2)) if u is None else np.array(u, dtype=np.float64, copy=True).reshape(n, 2)
+    out = {k: np.empty(n) for k in ("tof", "len", "miss_px")}
+    nm = np.empty(n, np.int32)
+    st = np.empty(n, np.int8)
+    flags = (WARM if warm else 0) | (FIXED if fixed else 0)
+    rc = lib().or3_trace(*args, elem.shape[0], _d(elem), _integ_code(integ), float(ds_px), float(tol_px),
+                         int(max_marches), int(max_steps), flags, n, _i(pairs), _d(uu), _d(out["tof"]),
+                         _d(out["len"]), _d(out["miss_px"]), _i(nm), _b(st))
+    if rc:
+        raise ValueError("bad medium")
+    out.update(u=uu, n_marches=nm, status=st)
+    return out
+
+
+def march3_free(medium, x0_px, d0, n_steps, integ="rk4", ds_px=0.25):
+    """n_steps free steps from pixel point x0 along d0: points [n+1, 3] (pixels)."""
+    args, keep = _medium3_args(medium)
+    x0 = np.ascontiguousarray(x0_px, dtype=np.float64)
+    d0 = np.ascontiguousarray(d0, dtype=np.float64)
+    pts = np.empty((n_steps + 1, 3))
+    if lib().or3_march_free(*args, _integ_code(integ), float(ds_px), _d(x0), _d(d0), int(n_steps), _d(pts)):
+        raise ValueError("bad medium")
+    return pts
+
+
+def jac0_3(elem, h, e, r, u):
+    """Homogeneous-medium Jacobian dg/du [2, 2] and the launch direction at u."""
+    elem = np.ascontiguousarray(elem, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    J, d = np.empty(4), np.empty(3)
+    if lib().or3_jac0(elem.shape[0], _d(elem), float(h), int(e), int(r), _d(u), _d(J), _d(d)):
+        raise ValueError("bad element")
+    return J.reshape(2, 2), d
+
+
+def interp3(medium, pts):
+    args, keep = _medium3_args(medium)
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    cv, G = np.empty(len(pts)), np.empty((len(pts), 3))
+    if lib().or3_interp(*args, len(pts), _d(pts), _d(cv), _d(G)):
+        raise ValueError("bad medium")
+    return cv, G
+
+
+def misfit3(medium, elem, e, r, u, integ="rk4", ds_px=0.25):
+    """One fixed-direction ray: (status, g [2], interception q [3] pixels)."""
+    args, keep = _medium3_args(medium)
+    elem = np.ascontiguousarray(elem, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    g, q = np.empty(2), np.empty(3)
+    st = lib().or3_misfit(*args, elem.shape[0], _d(elem), _integ_code(integ), float(ds_px), int(e), int(r), _d(u),
+                          _d(g), _d(q))
+    if st < 0:
+        raise ValueError("bad arguments")
+    return st, g, q

@@ -14,4 +14,11 @@ from .media import (  # noqa: F401
     smooth_random,
     striped_disc,
 )
+from .volume import (  # noqa: F401
+    node_coords3,
+    gaussian_inclusions3,
+    fisheye3,
+    linear_gradient3,
+    hemisphere_elements,
+)
 from .configs import CONFIGS, make_config, all_pairs, real_residual, complex_residual, c5_instances  # noqa: F401

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_pins as P
+from tests import test_oracle_pins3 as P3
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle_rt.c")
 
@@ -96,6 +97,57 @@ PINS = [
     lambda o: P.test_sart_consistent_system_converges(o),
     lambda o: P.test_sart_zero_rows_and_columns_take_no_part(o),
 ]
+
+
+SRC3 = os.path.join(os.path.dirname(oracle.__file__), "oracle_rt3.c")
+
+MUTATIONS3 = {
+    "rhs3_sign": ("k[3 + a] = -(G[a] - gd * y[3 + a]) / c;", "k[3 + a] = (G[a] - gd * y[3 + a]) / c;"),
+    "trilinear_axes_swapped": ("(by ? f[1] : 1.0 - f[1]) * (bz ? f[2] : 1.0 - f[2]);",
+                               "(by ? f[2] : 1.0 - f[2]) * (bz ? f[1] : 1.0 - f[1]);"),
+    "gradient3_wrong_stride": ("m->g[n + k] = diff1(m->c, idx3(m, ix, 0, iz), (size_t)m->nx, iy, m->ny);",
+                               "m->g[n + k] = diff1(m->c, idx3(m, 0, iy, iz), 1, ix, m->nx);"),
+    "jacobian3_length_term": ("dq[i] = L * dd[i] - 2.0 * d[i] * ed;", "dq[i] = L * dd[i];"),
+    "quadrature3_last_weight": ("acc += (ds + dsp) / 2.0 / c + dsp / 2.0 / cq;", "acc += ds / c + dsp / 2.0 / cq;"),
+    "sphere_crossing_root": ("double t = (B >= 0) ? (-2.0 * C) / (B + sqrt(D)) : (-B + sqrt(D)) / (2.0 * A);\n"
+                             "            if (t > 1.0) t = 1.0;\n            if (t < 0.0) t = 0.0;\n"
+                             "            for (int i = 0; i < 3; i++)",
+                             "double t = (B >= 0) ? (-B - sqrt(D)) / (2.0 * A) : (2.0 * C) / (-B + sqrt(D));\n"
+                             "            if (t > 1.0) t = 1.0;\n            if (t < 0.0) t = 0.0;\n"
+                             "            for (int i = 0; i < 3; i++)"),
+    "broyden_update_sign": ("J[0] += r0 * du[0] / uu;\n                J[1] += r0 * du[1] / uu;",
+                            "J[0] -= r0 * du[0] / uu;\n                J[1] -= r0 * du[1] / uu;"),
+}
+
+PINS3 = [
+    lambda o: P3.test3_homogeneous_straight_rays(o),
+    lambda o: P3.test3_homogeneous_jacobian_matches_traced_misfit(o),
+    lambda o: P3.test3_linear_gradient_closed_form(o, (50.0, -70.0, 80.0)),
+    lambda o: P3.test3_fisheye_antipodal_focus(o, "analytic", 0.003),
+    lambda o: P3.test3_fisheye_antipodal_focus(o, "grid", 0.05),
+    lambda o: P3.test3_fisheye_circles(o, "rk4", 1e-4),
+    lambda o: P3.test3_reciprocity_gaussian_volume(o),
+    lambda o: P3.test3_broyden_links_and_status_paths(o),
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS3))
+def test_planted_mistake_3d_is_caught(name, tmp_path, orc):
+    old, new = MUTATIONS3[name]
+    src = open(SRC3).read()
+    assert src.count(old) == 1, name
+    mut = tmp_path / "oracle_rt3_mut.c"
+    mut.write_text(src.replace(old, new))
+    lib = oracle.build(src=SRC, src3=str(mut), out=str(tmp_path / "liboracle_mut3.so"))
+    caught = None
+    with oracle.use_library(lib):
+        for k, pin in enumerate(PINS3):
+            try:
+                pin(oracle)
+            except (AssertionError, ValueError, IndexError, ZeroDivisionError):
+                caught = k
+                break
+    assert caught is not None, f"no 3-D pin fails with the planted mistake {name!r}"
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
