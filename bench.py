@@ -138,6 +138,39 @@ def run_sart(c_host, cfg, iters=10):
             "vs_hbm_peak_frac": bytes_it / (ms / iters * 1e-3) / 1e9 / PEAK_HBM_GBS}
 
 
+def run_3d(prec, steps=5, warmup=2):
+    """The 3-D workload (128^3 volume at 0.75 mm, 256-element hemispherical
+    bowl of radius 40 mm, 65,280 pairs, 12 Gaussian blobs): linked tracing from
+    the straight ray with Broyden-like updates (Sec. 3.4), ms per call and
+    linked rays/s."""
+    import torch
+
+    import paper_2511_18511_amd as rtx
+
+    cfg, c = synth.make_config3("c6_hemi_128")
+    el = synth.hemisphere_elements(cfg["n_elem"], cfg["radius"])
+    dev = torch.device("cuda", 0)
+    cd = torch.from_numpy(c).to(dev)
+    plan = rtx.Plan3(cfg["n"], cfg["n"], cfg["n"], cfg["h"], el, prec=prec, integ=cfg["integ"], ds_px=cfg["ds_px"],
+                     tol_px=cfg["tol_px"], max_marches=cfg["max_marches"])
+    for _ in range(warmup):
+        out = plan.trace(cd)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        out = plan.trace(cd)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = out["status"].cpu().numpy()
+    rk, rays = plan.stats()
+    plan.close()
+    return {"prec": prec, "pairs": plan.n_all, "ms_per_call": ms, "rays_per_s": plan.n_all / (ms * 1e-3),
+            "linked_fraction": float(np.mean(st == 0)), "mean_marches": float(out["n_marches"].double().mean()),
+            "max_marches": int(out["n_marches"].max()), "rk_steps": int(rk), "rays_traced": int(rays)}
+
+
 def cpu_baseline(c, cfg, resid, max_seconds=30.0):
     """The FP64 oracle on the host cores: linked trace + adjoint of the same
     workload, pairs split over a thread pool (the oracle releases the GIL)."""
@@ -205,6 +238,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--fan-only", action="store_true", help="skip the straight-start comparison runs")
     ap.add_argument("--no-sart", action="store_true", help="skip the SART measurement")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device copy (the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profile)")
@@ -249,6 +283,13 @@ def main():
 
     roof["traffic"] = measured_traffic()
     sart = None if args.no_sart else run_sart(c, cfg)
+    w3 = None
+    if not args.no_3d:
+        w3 = {p: run_3d(p) for p in ("f32c",) + (() if args.no_f64 else ("f64",))}
+        for p, r in w3.items():
+            print(f"# 3-D {p}: {r['ms_per_call']:.3f} ms per linked trace of {r['pairs']} pairs, "
+                  f"{r['rays_per_s'] / 1e6:.2f} M rays/s, {r['mean_marches']:.2f} rays/pair (max {r['max_marches']})",
+                  file=sys.stderr, flush=True)
     if sart:
         print(f"# SART: setup {sart['setup_ms']:.3f} ms, {sart['ms_per_iteration']:.3f} ms/iteration on "
               f"{sart['nnz']} entries ({sart['achieved_GBs']:.0f} GB/s)", file=sys.stderr, flush=True)
@@ -278,6 +319,9 @@ def main():
         "straight_start": {p: runs[(p, False)] for p, fan in runs if not fan},
         "gather": gather,
         "sart": sart,
+        "hemisphere_3d": ({"workload": "128^3 volume at 0.75 mm, 12 Gaussian blobs on 1500 m/s, 256-element "
+                                       "hemispherical bowl of radius 40 mm, all 65,280 ordered pairs, RK4 ds=0.25 px, "
+                                       "Broyden-like linking to 1e-3 px from the straight ray", **w3} if w3 else None),
     }
     print(json.dumps(line))
 

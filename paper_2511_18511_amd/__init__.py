@@ -314,6 +314,91 @@ class Batch:
             pass
 
 
+class Plan3:
+    """3-D tracing between point transducers on a sphere (hemispherical arrays)
+    through a sound-speed volume, with Broyden-like linking (Sec. 3.4).
+
+    elem: float64 [n_elem, 3] host array (metres from the grid centre, all on
+    one sphere); lengths in metres, ``ds_px``/``tol_px`` in grid pixels."""
+
+    def __init__(self, nx, ny, nz, h, elem, prec="f32c", integ="rk4", ds_px=0.25, tol_px=1e-3, max_marches=30,
+                 max_steps=0, max_pairs=None):
+        import numpy as np
+
+        self.nx, self.ny, self.nz, self.h = int(nx), int(ny), int(nz), float(h)
+        self.elem = np.ascontiguousarray(elem, dtype=np.float64).reshape(-1, 3)
+        self.n_elem = self.elem.shape[0]
+        self.prec = prec
+        self.n_all = self.n_elem * (self.n_elem - 1)
+        self.max_pairs = int(max_pairs or self.n_all)
+        self._opts = dict(integ=integ, ds_px=ds_px, tol_px=tol_px, max_marches=max_marches, max_steps=max_steps)
+        self._grid = B.rtx3_grid(self.nx, self.ny, self.nz, self.h)
+        self._handle = B.rtx3_plan_create(self._grid, self.elem, self._make_opts(0), self.max_pairs)
+
+    def _make_opts(self, flags, **over):
+        o = dict(self._opts, **over)
+        return B.rtx_opts(PRECISIONS[self.prec], INTEGRATORS[o["integ"]], float(o["ds_px"]), float(o["tol_px"]),
+                          int(o["max_marches"]), int(o["max_steps"]), int(flags))
+
+    def close(self):
+        if getattr(self, "_handle", None):
+            B.rtx3_plan_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_medium(self, c):
+        _dev_check(c, torch.float64, (self.nz, self.ny, self.nx), "c")
+        B.rtx3_set_medium(self._handle, _ptr(c), _stream())
+
+    def trace(self, c=None, pairs=None, u=None, warm=False, fixed=False, **over):
+        """Linked (or warm-started, or fixed-direction) tracing: dict of device
+        tensors u [n, 2], tof (s), len (m), miss_px, n_marches, status."""
+        if c is not None:
+            _dev_check(c, torch.float64, (self.nz, self.ny, self.nx), "c")
+        if pairs is None:
+            n = self.n_all
+        else:
+            _dev_check(pairs, torch.int32, None, "pairs")
+            n = pairs.shape[0]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = {
+            "u": torch.zeros(n, 2, dtype=torch.float64, device=dev),
+            "tof": torch.empty(n, dtype=torch.float64, device=dev),
+            "len": torch.empty(n, dtype=torch.float64, device=dev),
+            "miss_px": torch.empty(n, dtype=torch.float64, device=dev),
+            "n_marches": torch.empty(n, dtype=torch.int32, device=dev),
+            "status": torch.empty(n, dtype=torch.int8, device=dev),
+        }
+        if u is not None:
+            out["u"].copy_(u)
+        flags = (B.RTX_WARM_START if warm else 0) | (B.RTX_FIXED_ANGLE if fixed else 0)
+        B.rtx3_plan_set_opts(self._handle, self._make_opts(flags, **over))
+        B.rtx3_trace_rays(self._handle, _ptr(c), _ptr(pairs), n, _ptr(out["u"]), _ptr(out["tof"]), _ptr(out["len"]),
+                          _ptr(out["miss_px"]), _ptr(out["n_marches"]), _ptr(out["status"]), _stream())
+        return out
+
+    def march(self, x0, d0, n_steps, c=None, **over):
+        """Free march: float64 [n, n_steps + 1, 3] positions in metres."""
+        if c is not None:
+            _dev_check(c, torch.float64, (self.nz, self.ny, self.nx), "c")
+        n = x0.shape[0]
+        _dev_check(x0, torch.float64, (n, 3), "x0")
+        _dev_check(d0, torch.float64, (n, 3), "d0")
+        pts = torch.empty(n, int(n_steps) + 1, 3, dtype=torch.float64, device=x0.device)
+        B.rtx3_plan_set_opts(self._handle, self._make_opts(0, **over))
+        B.rtx3_march_free(self._handle, _ptr(c), n, _ptr(x0), _ptr(d0), int(n_steps), _ptr(pts), _stream())
+        return pts
+
+    def stats(self):
+        """(RK steps, rays) of the last trace call."""
+        return B.rtx3_plan_stats(self._handle)
+
+
 def trace_rays(c, h, n_elem, radius, phi0=0.0, pairs=None, theta=None, warm=False, fixed=False, **opts):
     """One-shot linked tracing of a float64 [ny, nx] device medium."""
     ny, nx = c.shape

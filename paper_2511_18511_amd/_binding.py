@@ -20,11 +20,18 @@ RTX_RAY_LINKED, RTX_RAY_NOT_CONVERGED, RTX_RAY_NO_HIT, RTX_RAY_BAD_INPUT = 0, 1,
 EXPORTS = ("rtx_plan_create", "rtx_plan_destroy", "rtx_plan_set_opts", "rtx_set_medium", "rtx_trace_rays",
            "rtx_tof_forward", "rtx_march_free", "rtx_paraxial", "rtx_sart", "rtx_tof_adjoint", "rtx_plan_stats", "rtx_plan_region_stats", "rtx_plan_timing",
            "rtx_plan_timings", "rtx_plan_set_launch", "rtx_batch_create",
-           "rtx_batch_run", "rtx_batch_times", "rtx_batch_destroy", "rtx_last_error")
+           "rtx_batch_run", "rtx_batch_times", "rtx_batch_destroy", "rtx_last_error",
+           # include/rtx3d.h
+           "rtx3_plan_create", "rtx3_plan_destroy", "rtx3_plan_set_opts", "rtx3_set_medium", "rtx3_trace_rays",
+           "rtx3_march_free", "rtx3_plan_stats", "rtx3_last_error")
 
 
 class rtx_grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("h", C.c_double)]
+
+
+class rtx3_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h", C.c_double)]
 
 
 class rtx_ring(C.Structure):
@@ -81,9 +88,15 @@ def load():
     L.rtx_batch_run.argtypes = [vp, vp]
     L.rtx_batch_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.rtx_batch_destroy.argtypes = [vp]
-    L.rtx_last_error.restype = C.c_char_p
+    L.rtx3_plan_create.argtypes = [C.POINTER(vp), C.POINTER(rtx3_grid), i32, vp, C.POINTER(rtx_opts), i64]
+    L.rtx3_plan_destroy.argtypes = [vp]
+    L.rtx3_plan_set_opts.argtypes = [vp, C.POINTER(rtx_opts)]
+    L.rtx3_set_medium.argtypes = [vp, vp, vp]
+    L.rtx3_trace_rays.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.rtx3_march_free.argtypes = [vp, vp, i64, vp, vp, C.c_int32, vp, vp]
+    L.rtx3_plan_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
     for name in EXPORTS:
-        getattr(L, name).restype = C.c_char_p if name == "rtx_last_error" else C.c_int
+        getattr(L, name).restype = C.c_char_p if name.endswith("last_error") else C.c_int
     _lib = L
     return L
 
@@ -92,6 +105,48 @@ def check(code):
     if code != RTX_OK:
         raise RtxError(code, load().rtx_last_error().decode())
     return code
+
+
+def check3(code):
+    if code != RTX_OK:
+        raise RtxError(code, load().rtx3_last_error().decode())
+    return code
+
+
+def rtx3_plan_create(grid, elem_host, opts, max_pairs):
+    """elem_host: float64 [n][3] numpy array (metres)."""
+    h = C.c_void_p()
+    e = elem_host
+    check3(load().rtx3_plan_create(C.byref(h), C.byref(grid), int(e.shape[0]), C.c_void_p(e.ctypes.data),
+                                   C.byref(opts), int(max_pairs)))
+    return h
+
+
+def rtx3_plan_destroy(plan):
+    return check3(load().rtx3_plan_destroy(plan))
+
+
+def rtx3_plan_set_opts(plan, opts):
+    return check3(load().rtx3_plan_set_opts(plan, C.byref(opts)))
+
+
+def rtx3_set_medium(plan, c, stream):
+    return check3(load().rtx3_set_medium(plan, c, stream))
+
+
+def rtx3_trace_rays(plan, c, pairs, n_pairs, u, tof, len_, miss_px, n_marches, status, stream):
+    return check3(load().rtx3_trace_rays(plan, c, pairs, int(n_pairs), u, tof, len_, miss_px, n_marches, status,
+                                         stream))
+
+
+def rtx3_march_free(plan, c, n_rays, x0, d0, n_steps, pts, stream):
+    return check3(load().rtx3_march_free(plan, c, int(n_rays), x0, d0, int(n_steps), pts, stream))
+
+
+def rtx3_plan_stats(plan):
+    a, b = C.c_int64(), C.c_int64()
+    check3(load().rtx3_plan_stats(plan, C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def rtx_plan_create(grid, ring, opts, max_pairs):

@@ -21,4 +21,4 @@ from .volume import (  # noqa: F401
     linear_gradient3,
     hemisphere_elements,
 )
-from .configs import CONFIGS, make_config, all_pairs, real_residual, complex_residual, c5_instances  # noqa: F401
+from .configs import CONFIGS, CONFIGS3, make_config, make_config3, all_pairs, real_residual, complex_residual, c5_instances  # noqa: F401

@@ -9,7 +9,7 @@ import math
 
 import numpy as np
 
-from . import media
+from . import media, volume
 
 # Seeds: media 1000 + config number, residuals 2000 + config number,
 # batched instance i: 3000 + i.
@@ -38,6 +38,26 @@ CONFIGS = {
         resid_seed=2004, n_freq=64, f_lo=0.5e6, f_hi=1.5e6,
     ),
 }
+
+
+# 3-D workload: a hemispherical bowl of point transducers around a volume of
+# Gaussian blobs (the 3-D acquisition geometries of the ToF method, Sec. 3).
+CONFIGS3 = {
+    "c6_hemi_128": dict(
+        n=128, h=0.75e-3, n_elem=256, radius=0.040,
+        medium_args=dict(seed=1006, r_max=0.025),
+        integ="rk4", ds_px=0.25, tol_px=1e-3, max_marches=30,
+    ),
+}
+
+
+def make_config3(name):
+    """Return (cfg, c) for a named 3-D workload; c is float64 [n, n, n] and the
+    elements are volume.hemisphere_elements(n_elem, radius)."""
+    cfg = dict(CONFIGS3[name])
+    cfg["name"] = name
+    n, h = cfg["n"], cfg["h"]
+    return cfg, volume.gaussian_inclusions3(n, n, n, h, **cfg["medium_args"])
 
 
 def build_medium(cfg):

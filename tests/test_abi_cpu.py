@@ -1,5 +1,5 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads, exports
-every function include/rtx.h declares, and the Python structs match the C
+every function include/rtx.h and include/rtx3d.h declare, and the Python structs match the C
 layout."""
 import ctypes as C
 import os
@@ -9,7 +9,7 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rtx.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("rtx.h", "rtx3d.h")]
 
 
 @pytest.fixture(scope="module")
@@ -22,9 +22,9 @@ def lib():
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "\n".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(rtx_\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(rtx3?_\w+)\s*\(", src, flags=re.M)))
 
 
 def test_header_declares_the_boundary():
@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(lib):
     names = declared_functions()
     assert sorted(_binding.EXPORTS) == names
     out = subprocess.run(["nm", "-D", "--defined-only", _binding.LIB_PATH], capture_output=True, text=True).stdout
-    exported = set(re.findall(r" T (rtx_\w+)", out))
+    exported = set(re.findall(r" T (rtx3?_\w+)", out))
     assert set(names) <= exported
     for n in names:
         assert hasattr(lib, n)
