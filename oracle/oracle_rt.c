@@ -593,19 +593,25 @@ static void link_pair(const Medium *m, const Ring *ring, const Opts *o, int e, i
 /* Fan start (an initial-guess option; the secant and its safeguards are
  * unchanged).  The straight-ray rays of all receivers of one emitter sample the
  * same function: the hit angle H(theta) = mod(phi_hit - phi_e, 2 pi) of a ray
- * launched at theta.  For receiver r with target D_r = mod(phi_r - phi_e, 2 pi)
- * the samples give G_j = H_j - D_r at the straight angles theta_j of the
- * receivers at offsets j = 1..n-1 (increasing in j).  The linking of r starts
- * from its own straight ray (counted as its first traced ray):
- *   - if that ray already links, it is the result;
- *   - else, the sign change of G over consecutive samples (j, j+1) nearest to
- *     r's own offset (searching j = own, own+1, own-1-1, ... outward) seeds the
- *     secant: the end with the larger |G| then the one with the smaller |G| are
- *     fed to the state machine as hitting rays, whose next angle is their
- *     secant (linear) interpolation inside the bracket they form;
- *   - with no such bracket, the own ray is fed alone (homogeneous Newton
- *     second point), or, if it did not hit, the trapped-ray back-off applies.
- * Only rays traced for this pair enter its best-ray record. */
+ * launched at theta.  These fan rays only seed the linking, so they are traced
+ * with a coarser step (fan_step: four tracing steps, at most a pixel) and are
+ * not counted among the pair's rays.  For receiver r with target
+ * D_r = mod(phi_r - phi_e, 2 pi) the samples give G_j = H_j - D_r at the
+ * straight angles theta_j of the receivers at offsets j = 1..n-1 (increasing in
+ * j); the linking of r then traces at the full resolution:
+ *   - the sign change of G over consecutive samples (j, j+1) nearest to r's own
+ *     offset (searching j = own, own+1, own-1-1, ... outward) seeds the secant:
+ *     the end with the larger |G| then the one with the smaller |G| are fed to
+ *     the state machine as hitting rays, whose next angle is their secant
+ *     (linear) interpolation inside the bracket they form, or the cubic
+ *     refinement below;
+ *   - with no such bracket, the own fan sample is fed alone (homogeneous Newton
+ *     second point); if it did not hit, the trapped-ray back-off applies; if it
+ *     met bad input, the straight angle itself is traced;
+ *   - the fed samples enter the secant's two latest points but not its sign
+ *     bracket, which only full-resolution rays establish.
+ * Only rays traced for this pair at the full resolution enter its best-ray
+ * record and its ray count. */
 typedef struct {
     double g, T, L; /* own straight ray: misfit (own receiver), time, length */
     int st;
@@ -648,28 +654,8 @@ static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, in
     double Dr = mod2pi(elem_angle(ring, rcv) - pe);
     double th_own = straight_angle(ring, e, rcv);
     const FanSample *own = &row[jr - 1];
-    if (own->st == ST_BAD_INPUT) {
-        out->theta = th_own;
-        out->T = out->L = out->miss = NAN;
-        out->n_marches = 1;
-        out->status = ST_BAD_INPUT;
-        return;
-    }
     LinkState s;
     link_init(&s, th_own);
-    if (own->st == ST_LINKED) {
-        double miss = fabs(own->g) * ring->radius_px;
-        link_best(&s, th_own, miss, own->T, own->L);
-        if (miss <= o->tol) {
-            out->theta = th_own;
-            out->T = own->T;
-            out->L = own->L;
-            out->miss = miss;
-            out->n_marches = 1;
-            out->status = ST_LINKED;
-            return;
-        }
-    }
     /* G_j relative to this receiver, NaN where the sample did not hit */
     double *G = (double *)malloc(sizeof(double) * (n - 1));
     double *TH = (double *)malloc(sizeof(double) * (n - 1));
@@ -701,13 +687,22 @@ static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, in
         if (fan_cubic(G, TH, n - 1, found, &thc)) th = thc;
     } else if (own->st == ST_LINKED) {
         th = link_after_hit(&s, th_own, own->g);
-    } else {
+    } else if (own->st == ST_NO_HIT) {
         th = link_after_miss(&s, th_own);
+    } else {
+        th = th_own;
     }
+    /* the coarse samples steer the secant but do not bound it: only rays traced
+       at the full resolution establish the sign bracket */
+    s.have_neg = s.have_pos = 0;
     free(G);
     free(TH);
-    link_run(m, ring, o, e, rcv, &s, th, 1, out);
+    link_run(m, ring, o, e, rcv, &s, th, 0, out);
 }
+
+/* Step of the fan rays: four times the tracing step, at most one pixel (and
+   never below the tracing step); the step limit scales with it. */
+static double fan_step(double ds) { return fmax(ds, fmin(4.0 * ds, 1.0)); }
 
 /* --------------------------------------------------------------- exported -- */
 static int setup(int kind, int nx, int ny, double h, const double *c, const double *mpar, int n_elem,
@@ -787,11 +782,14 @@ int or_trace(int kind, int nx, int ny, double h, const double *c, const double *
             }
         }
         FanSample *row = (FanSample *)malloc(sizeof(FanSample) * (n - 1));
+        Opts of = o; /* the fan's coarse rays */
+        of.ds = fan_step(o.ds);
+        of.max_steps = (int)ceil(o.max_steps * o.ds / of.ds);
         for (int e = 0; e < n; e++) {
             for (int j = 1; j < n; j++) { /* straight rays of emitter e, by offset */
                 int k = (e + j) % n;
                 FanSample *f = &row[j - 1];
-                f->st = trace_at(&m, &ring, &o, e, k, straight_angle(&ring, e, k), &f->g, &f->T, &f->L, NULL);
+                f->st = trace_at(&m, &ring, &of, e, k, straight_angle(&ring, e, k), &f->g, &f->T, &f->L, NULL);
             }
             for (int j = 1; j < n; j++) {
                 int r = (e + j) % n;

@@ -1026,24 +1026,9 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
                 link_reset(L, th0);
                 double th = th0;
                 if (FAN) {
-                    // the pair's own straight ray was traced by the fixed pass
-                    L.n_marches = 1;
-                    int st0 = a.f_st[q];
-                    if (st0 == RTX_RAY_BAD_INPUT) {
-                        write_pair(a, q, th0, NAN, NAN, NAN, 1, RTX_RAY_BAD_INPUT);
-                        goto next;
-                    }
-                    if (st0 == RTX_RAY_LINKED) {
-                        double miss = fabs(a.f_g[q]) * gg.R;
-                        L.best_miss = miss;
-                        L.best_th = th0;
-                        L.best_T = a.f_T[q];
-                        L.best_L = a.f_L[q];
-                        if (miss <= a.tol) {
-                            write_pair(a, q, th0, a.f_T[q], a.f_L[q], miss, 1, RTX_RAY_LINKED);
-                            goto next;
-                        }
-                    }
+                    // the coarse fan rays (a seed only, not counted) bracket the
+                    // root; every ray of the pair is traced here
+                    const int st0 = a.f_st[q];
                     const FanSeed sd = a.seed[q];
                     if (sd.found) {
                         L.th = sd.th_far;
@@ -1053,17 +1038,11 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
                         if (sd.cubic) th = sd.th_first;
                     } else if (st0 == RTX_RAY_LINKED) {
                         th = link_next_hit(L, a.f_g[q]);
-                    } else {
+                    } else if (st0 == RTX_RAY_NO_HIT) {
                         th = 0.5 * th0;
                     }
                     L.th = th;
-                    if (L.n_marches >= a.max_marches) {  // only the straight ray was allowed
-                        if (L.best_miss < INFINITY)
-                            write_pair(a, q, L.best_th, L.best_T, L.best_L, L.best_miss, 1, RTX_RAY_NOT_CONVERGED);
-                        else
-                            write_pair(a, q, th0, NAN, NAN, NAN, 1, RTX_RAY_NO_HIT);
-                        goto next;
-                    }
+                    L.have_neg = L.have_pos = 0;  // the coarse samples do not bound the secant
                 }
                 start_ray<R, COMP>(ray, gg, em, th);
                 if (!BSP) slots_prime(m, C, ray, ds, INTEG);
@@ -1071,7 +1050,6 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
                 return;
             }
             write_pair(a, q, a.theta[q], NAN, NAN, NAN, 0, RTX_RAY_BAD_INPUT);
-        next:
             if (BATCH) mark_done(B, k);
             p += stride;
         }
@@ -2473,10 +2451,12 @@ int grid_blocks(const rtx_plan_s *P, K kernel, int64_t n)
 }
 
 template <class R, bool COMP, bool FAN = false>
-int launch_trace(rtx_plan_s *P, const TraceArgs &A, hipStream_t s, int region = 0, int slot = RTX_SLOT_TRACE)
+int launch_trace(rtx_plan_s *P, const TraceArgs &A, hipStream_t s, int region = 0, int slot = RTX_SLOT_TRACE,
+                 double ds_px = 0.0)
 {
     Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
     Geo g = make_geo(P);
+    if (ds_px > 0.0) g.ds = ds_px;
     auto kern = P->bsp ? (P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false, FAN, true>
                                                    : k_trace<R, COMP, 2, false, FAN, true>)
                        : (P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false, FAN> : k_trace<R, COMP, 2, false, FAN>);
@@ -2504,6 +2484,9 @@ int launch_fan(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
             hipMalloc(&P->f_seed, sizeof(FanSeed) * P->max_pairs) != hipSuccess)
             return fail(RTX_E_NOMEM, "fan-start workspace");
     }
+    // the fan rays seed the linking only: four tracing steps per fan step, at
+    // most a pixel (never below the tracing step), the step limit scaled alike
+    const double ds_fan = std::max(P->opts.ds_px, std::min(4.0 * P->opts.ds_px, 1.0));
     TraceArgs A1 = A;
     A1.flags = RTX_FIXED_ANGLE | kStraight;
     A1.tof = P->f_T;
@@ -2512,7 +2495,8 @@ int launch_fan(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
     A1.n_marches = nullptr;
     A1.status = P->f_st;
     A1.gsig = P->f_g;
-    if (int rc = launch_trace<R, COMP>(P, A1, s, 0, RTX_SLOT_TRACE)) return rc;
+    A1.max_steps = (int)ceil(A.max_steps * P->opts.ds_px / ds_fan);
+    if (int rc = launch_trace<R, COMP>(P, A1, s, 0, RTX_SLOT_TRACE, ds_fan)) return rc;
     Geo g = make_geo(P);
     if (int rc = time_mark(P, RTX_SLOT_FAN_SEED, 0, s)) return rc;
     hipLaunchKernelGGL(k_fan_seed, dim3(P->ring.n_elem), dim3(kBlock), sizeof(double) * (P->ring.n_elem - 1), s, g,
