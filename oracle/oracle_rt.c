@@ -645,6 +645,158 @@ static int fan_cubic(const double *G, const double *TH, int m, int a, double *th
     return 1;
 }
 
+/* The four samples of smallest |g| seen by a fan-started pair: its fan seed
+ * samples (bracket and outer neighbours, in order) and then every hitting ray
+ * it traced (round by round, ray 0 first).  A new sample replaces the kept one
+ * of largest |g| (the later of equal ones) when its |g| is strictly smaller. */
+typedef struct {
+    double th[4], g[4];
+    int id[4], n, next;
+} Top4;
+
+static void top4_push(Top4 *t, double th, double g)
+{
+    int id = t->next++;
+    if (t->n < 4) {
+        t->th[t->n] = th;
+        t->g[t->n] = g;
+        t->id[t->n] = id;
+        t->n++;
+        return;
+    }
+    int w = 0;
+    for (int k = 1; k < 4; k++)
+        if (fabs(t->g[k]) > fabs(t->g[w]) || (fabs(t->g[k]) == fabs(t->g[w]) && t->id[k] > t->id[w])) w = k;
+    if (fabs(g) < fabs(t->g[w])) {
+        t->th[w] = th;
+        t->g[w] = g;
+        t->id[w] = id;
+    }
+}
+
+/* Inverse cubic through the four kept samples: ordered by angle they must be
+ * strictly increasing in angle and strictly monotone in g; the zero of the
+ * cubic interpolating theta as a function of g is accepted if it lies strictly
+ * between the outer two angles and inside the sign bracket of the traced rays,
+ * when there is one (returns 1 and the angle). */
+static int top4_estimate(const Top4 *t, const LinkState *s, double *th)
+{
+    if (t->n < 4) return 0;
+    double a[4], g[4];
+    for (int i = 0; i < 4; i++) {
+        a[i] = t->th[i];
+        g[i] = t->g[i];
+    }
+    for (int i = 1; i < 4; i++) /* insertion sort by angle */
+        for (int j = i; j > 0 && a[j] < a[j - 1]; j--) {
+            double x = a[j];
+            a[j] = a[j - 1];
+            a[j - 1] = x;
+            x = g[j];
+            g[j] = g[j - 1];
+            g[j - 1] = x;
+        }
+    int up = g[1] > g[0];
+    for (int i = 0; i < 3; i++) {
+        if (!(a[i + 1] > a[i])) return 0;
+        if (up ? !(g[i + 1] > g[i]) : !(g[i + 1] < g[i])) return 0;
+    }
+    double v = 0.0;
+    for (int i = 0; i < 4; i++) {
+        double w = 1.0;
+        for (int q = 0; q < 4; q++)
+            if (q != i) w *= -g[q] / (g[i] - g[q]);
+        v += w * a[i];
+    }
+    if (!(v > a[0] && v < a[3])) return 0;
+    if (s->have_neg && s->have_pos) {
+        double lo = s->th_neg < s->th_pos ? s->th_neg : s->th_pos;
+        double hi = s->th_neg < s->th_pos ? s->th_pos : s->th_neg;
+        if (!(v > lo && v < hi)) return 0;
+    }
+    *th = v;
+    return 1;
+}
+
+/* Linking in rounds of two rays (the fan start's iteration).  A round traces
+ * the primary angle c0 and a hedge c1 = c0 - (c0 - ref) / 10, a tenth of the way
+ * back towards the latest fed sample ref (or the start angle), so that a round
+ * that does not link leaves two close samples, i.e. a local derivative, for the
+ * next secant step.  After a round: a ray with bad input ends the pair (BAD);
+ * every hitting ray enters the best-ray record (ray 0 first); the hitting ray of
+ * smallest miss within the tolerance is the result; after max_marches rays the
+ * best ray is returned (NOT_CONVERGED), or NO_HIT; otherwise the hitting rays
+ * are fed to the secant state machine in order of decreasing |g| (ray 0 first on
+ * a tie), the last feed giving the next primary angle, or, when neither hit, the
+ * trapped-ray back-off from c0 gives it; when a ray hit, the inverse cubic
+ * through the four samples of smallest |g| (top4_estimate) replaces the
+ * secant's angle where it is defined.  Both rays count as traced rays. */
+static void link_pairs(const Medium *m, const Ring *ring, const Opts *o, int e, int rcv, LinkState *s, Top4 *t4,
+                       double th, LinkOut *out)
+{
+    out->n_marches = 0;
+    for (;;) {
+        double ref = s->nvalid > 0 ? s->thb : s->th0;
+        double c[2] = {th, th == ref ? th + 1e-4 : th - 0.1 * (th - ref)};
+        double g[2], T[2], L[2];
+        int st[2];
+        for (int j = 0; j < 2; j++) st[j] = trace_at(m, ring, o, e, rcv, c[j], &g[j], &T[j], &L[j], NULL);
+        out->n_marches += 2;
+        if (st[0] == ST_BAD_INPUT || st[1] == ST_BAD_INPUT) {
+            out->theta = s->th0;
+            out->T = out->L = out->miss = NAN;
+            out->status = ST_BAD_INPUT;
+            return;
+        }
+        int lk = -1;
+        double lmiss = INFINITY;
+        for (int j = 0; j < 2; j++) {
+            if (st[j] != ST_LINKED) continue;
+            double miss = fabs(g[j]) * ring->radius_px;
+            link_best(s, c[j], miss, T[j], L[j]);
+            if (miss <= o->tol && miss < lmiss) {
+                lk = j;
+                lmiss = miss;
+            }
+        }
+        if (lk >= 0) {
+            out->theta = c[lk];
+            out->T = T[lk];
+            out->L = L[lk];
+            out->miss = lmiss;
+            out->status = ST_LINKED;
+            return;
+        }
+        if (out->n_marches >= o->max_marches) break;
+        int hit0 = st[0] == ST_LINKED, hit1 = st[1] == ST_LINKED;
+        for (int j = 0; j < 2; j++)
+            if (st[j] == ST_LINKED) top4_push(t4, c[j], g[j]);
+        if (hit0 && hit1) {
+            int first = fabs(g[0]) >= fabs(g[1]) ? 0 : 1;
+            link_after_hit(s, c[first], g[first]);
+            th = link_after_hit(s, c[1 - first], g[1 - first]);
+        } else if (hit0 || hit1) {
+            int j = hit0 ? 0 : 1;
+            th = link_after_hit(s, c[j], g[j]);
+        } else {
+            th = link_after_miss(s, c[0]);
+        }
+        double v;
+        if ((hit0 || hit1) && top4_estimate(t4, s, &v)) th = v;
+    }
+    if (s->best_miss < INFINITY) {
+        out->theta = s->best_th;
+        out->T = s->best_T;
+        out->L = s->best_L;
+        out->miss = s->best_miss;
+        out->status = ST_NOT_CONVERGED;
+    } else {
+        out->theta = s->th0;
+        out->T = out->L = out->miss = NAN;
+        out->status = ST_NO_HIT;
+    }
+}
+
 static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, int rcv, const FanSample *row,
                      LinkOut *out)
 {
@@ -656,6 +808,8 @@ static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, in
     const FanSample *own = &row[jr - 1];
     LinkState s;
     link_init(&s, th_own);
+    Top4 t4;
+    memset(&t4, 0, sizeof t4);
     /* G_j relative to this receiver, NaN where the sample did not hit */
     double *G = (double *)malloc(sizeof(double) * (n - 1));
     double *TH = (double *)malloc(sizeof(double) * (n - 1));
@@ -685,6 +839,8 @@ static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, in
         th = link_after_hit(&s, TH[near], G[near]);
         double thc;
         if (fan_cubic(G, TH, n - 1, found, &thc)) th = thc;
+        for (int i = found - 1; i <= found + 2; i++)
+            if (i >= 0 && i <= n - 2 && G[i] == G[i]) top4_push(&t4, TH[i], G[i]);
     } else if (own->st == ST_LINKED) {
         th = link_after_hit(&s, th_own, own->g);
     } else if (own->st == ST_NO_HIT) {
@@ -697,7 +853,7 @@ static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, in
     s.have_neg = s.have_pos = 0;
     free(G);
     free(TH);
-    link_run(m, ring, o, e, rcv, &s, th, 0, out);
+    link_pairs(m, ring, o, e, rcv, &s, &t4, th, out);
 }
 
 /* Step of the fan rays: four times the tracing step, at most one pixel (and
