@@ -724,13 +724,16 @@ static int top4_estimate(const Top4 *t, const LinkState *s, double *th)
  * that does not link leaves two close samples, i.e. a local derivative, for the
  * next secant step.  After a round: a ray with bad input ends the pair (BAD);
  * every hitting ray enters the best-ray record (ray 0 first); the hitting ray of
- * smallest miss within the tolerance is the result; after max_marches rays the
- * best ray is returned (NOT_CONVERGED), or NO_HIT; otherwise the hitting rays
+ * smallest miss within the tolerance is the result; after max_marches rounds
+ * (2 max_marches rays: the rounds, not the rays, are sequential) the best ray
+ * is returned (NOT_CONVERGED), or NO_HIT; otherwise the hitting rays
  * are fed to the secant state machine in order of decreasing |g| (ray 0 first on
  * a tie), the last feed giving the next primary angle, or, when neither hit, the
- * trapped-ray back-off from c0 gives it; when a ray hit, the inverse cubic
- * through the four samples of smallest |g| (top4_estimate) replaces the
- * secant's angle where it is defined.  Both rays count as traced rays. */
+ * trapped-ray back-off from c0 gives it; after the first two rounds, when a
+ * ray hit, the inverse cubic through the four samples of smallest |g|
+ * (top4_estimate) replaces the secant's angle where it is defined (later rounds
+ * keep the safeguarded secant alone, whose bracket halving does not stall on a
+ * misfit that jumps).  Both rays count as traced rays. */
 static void link_pairs(const Medium *m, const Ring *ring, const Opts *o, int e, int rcv, LinkState *s, Top4 *t4,
                        double th, LinkOut *out)
 {
@@ -767,7 +770,7 @@ static void link_pairs(const Medium *m, const Ring *ring, const Opts *o, int e, 
             out->status = ST_LINKED;
             return;
         }
-        if (out->n_marches >= o->max_marches) break;
+        if (out->n_marches >= 2 * o->max_marches) break; /* max_marches rounds */
         int hit0 = st[0] == ST_LINKED, hit1 = st[1] == ST_LINKED;
         for (int j = 0; j < 2; j++)
             if (st[j] == ST_LINKED) top4_push(t4, c[j], g[j]);
@@ -782,7 +785,7 @@ static void link_pairs(const Medium *m, const Ring *ring, const Opts *o, int e, 
             th = link_after_miss(s, c[0]);
         }
         double v;
-        if ((hit0 || hit1) && top4_estimate(t4, s, &v)) th = v;
+        if ((hit0 || hit1) && out->n_marches <= 4 && top4_estimate(t4, s, &v)) th = v;
     }
     if (s->best_miss < INFINITY) {
         out->theta = s->best_th;

@@ -795,6 +795,93 @@ __device__ __forceinline__ double link_next_hit(Link &L, double g)
     return nx;
 }
 
+// Keeps the compiler from moving memory accesses across this point.
+__device__ __forceinline__ void compiler_fence() { __asm__ volatile("" ::: "memory"); }
+
+// The four samples of smallest |g| of a fan-started pair: its fan samples (the
+// bracket and its outer neighbours, in order), then every hitting ray it traced
+// (round by round, ray 0 first).  A new sample replaces the kept one of largest
+// |g| (the later of equal ones) when its |g| is strictly smaller.
+struct Top4 {
+    double th[4], g[4];
+    int id[4], n, next;
+};
+
+__device__ __forceinline__ void top4_push(Top4 &t, double th, double g)
+{
+    const int id = t.next++;
+    if (t.n < 4) {
+        for (int k = 0; k < 4; k++)
+            if (k == t.n) {
+                t.th[k] = th;
+                t.g[k] = g;
+                t.id[k] = id;
+            }
+        t.n++;
+        return;
+    }
+    int w = 0;
+    for (int k = 1; k < 4; k++)
+        if (fabs(t.g[k]) > fabs(t.g[w]) || (fabs(t.g[k]) == fabs(t.g[w]) && t.id[k] > t.id[w])) w = k;
+    double gw = 0.0;
+    for (int k = 0; k < 4; k++)
+        if (k == w) gw = t.g[k];
+    if (fabs(g) < fabs(gw))
+        for (int k = 0; k < 4; k++)
+            if (k == w) {
+                t.th[k] = th;
+                t.g[k] = g;
+                t.id[k] = id;
+            }
+}
+
+__device__ __forceinline__ void cswap(double &a, double &b, double &ga, double &gb)
+{
+    if (b < a) {
+        double x = a;
+        a = b;
+        b = x;
+        x = ga;
+        ga = gb;
+        gb = x;
+    }
+}
+
+// Inverse cubic through the four kept samples (ordered by angle: strictly
+// increasing angles, strictly monotone g); its zero is accepted strictly
+// between the outer angles and inside the traced rays' sign bracket, if any.
+__device__ __forceinline__ bool top4_estimate(const Top4 &t, const Link &L, double &th)
+{
+    if (t.n < 4) return false;
+    double a0 = t.th[0], a1 = t.th[1], a2 = t.th[2], a3 = t.th[3];
+    double g0 = t.g[0], g1 = t.g[1], g2 = t.g[2], g3 = t.g[3];
+    cswap(a0, a1, g0, g1);
+    cswap(a2, a3, g2, g3);
+    cswap(a0, a2, g0, g2);
+    cswap(a1, a3, g1, g3);
+    cswap(a1, a2, g1, g2);
+    const double a[4] = {a0, a1, a2, a3}, g[4] = {g0, g1, g2, g3};
+    const bool up = g[1] > g[0];
+    for (int i = 0; i < 3; i++) {
+        if (!(a[i + 1] > a[i])) return false;
+        if (up ? !(g[i + 1] > g[i]) : !(g[i + 1] < g[i])) return false;
+    }
+    double v = 0.0;
+    for (int i = 0; i < 4; i++) {
+        double w = 1.0;
+        for (int q = 0; q < 4; q++)
+            if (q != i) w *= -g[q] / (g[i] - g[q]);
+        v += w * a[i];
+    }
+    if (!(v > a[0] && v < a[3])) return false;
+    if (L.have_neg && L.have_pos) {
+        const double lo = fmin(L.th_neg, L.th_pos), hi = fmax(L.th_neg, L.th_pos);
+        if (!(v > lo && v < hi)) return false;
+    }
+    th = v;
+    return true;
+}
+
 // ------------------------------------------------------------ trace kernel --
 // Fan start: the straight-ray rays of all receivers of an emitter sample one
 // function, the hit angle of a ray launched at theta; the nearest sign change of
@@ -802,7 +889,8 @@ __device__ __forceinline__ double link_next_hit(Link &L, double g)
 struct FanSeed {
     double th_far, g_far, th_near, g_near;  // bracket ends (larger |g| first)
     double th_first;                        // first linking angle (cubic), if `cubic`
-    int found, cubic;
+    double s_th[4], s_g[4];                 // the bracket and its outer neighbours that hit, in order
+    int found, cubic, n_s;
 };
 
 constexpr uint32_t kStraight = 1u << 16;  // internal: fixed pass at straight angles
@@ -1146,6 +1234,219 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
     block_sum2(n_steps, n_rays, A.stats);
 }
 
+// ------------------------------------------------- fan-started linking pass --
+// Linking in rounds of two rays: the two lanes 2i, 2i+1 of a wave own pair i
+// and keep identical copies of its linking state; each round lane 0 traces the
+// primary angle c0 and lane 1 the hedge c1 = c0 - (c0 - ref) / 10 (ref: the
+// latest fed sample, or the start angle), a tenth of the way back, so that a
+// round that does not link leaves two close samples for the next step.  A lane
+// whose ray ends posts its result to LDS and idles; when both have posted (a
+// wave ballot), both read the two results and take the same decision:
+//   bad input -> BAD; every hitting ray enters the best record (ray 0 first);
+//   the hitting ray of smallest miss within the tolerance -> LINKED; after
+//   max_marches rounds (the rounds are what is sequential) -> the best ray
+//   (NOT_CONVERGED) or NO_HIT; otherwise the
+//   hits are fed to the secant state in order of decreasing |g| (ray 0 first
+//   on a tie), or the back-off applies when neither hit, and after the first
+//   two rounds the inverse cubic through the four samples of smallest |g|
+//   (Top4) replaces the secant's angle where it is defined (later rounds keep
+//   the safeguarded secant, whose bracket halving copes with misfit jumps).  A second wave per SIMD costs the latency-bound
+//   trace nothing measurable, and the extra candidate removes most third rounds.
+template <class R, bool COMP, int INTEG, bool BSP = false>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+    k_link2(Medium<R> M, Geo g, TraceArgs A)
+{
+    __shared__ double s_th[kBlock], s_g[kBlock], s_T[kBlock], s_L[kBlock];
+    __shared__ int s_st[kBlock];
+    // the linking state is touched only at the end of a round: it lives in LDS,
+    // which keeps the marching registers within two waves per SIMD
+    __shared__ Link s_link[kBlock];
+    __shared__ Top4 s_top[kBlock];
+    __shared__ Emitter s_em[kBlock];
+    __shared__ double s_dr[kBlock];
+    const int lane = threadIdx.x, j = lane & 1, b0 = lane & ~1;
+    const int64_t stride = ((int64_t)gridDim.x * blockDim.x) >> 1;
+    int64_t p = ((int64_t)blockIdx.x * blockDim.x + lane) >> 1;
+    const R ds = (R)g.ds, R2 = (R)(g.R * g.R), cx = (R)g.cx, cy = (R)g.cy;
+    unsigned long long n_steps = 0, n_rays = 0;
+
+    Ray<R> ray;
+    Slot<R> C[3];
+    Link &L = s_link[lane];
+    Top4 &t4 = s_top[lane];
+    Emitter &em = s_em[lane];
+    double &dr = s_dr[lane];
+    int e = 0, r = 0;
+    double mine = 0;
+    bool active = false, waiting = false;
+
+    auto round_start = [&](double th) {
+        const double ref = L.nvalid > 0 ? L.thb : L.th0;
+        mine = j == 0 ? th : (th == ref ? th + 1e-4 : th - 0.1 * (th - ref));
+        start_ray<R, COMP>(ray, g, em, mine);
+        if (!BSP) slots_prime(M, C, ray, ds, INTEG);
+    };
+    auto next_pair = [&]() {
+        while (p < A.n_pairs) {
+            if (!pair_of(A, g, p, e, r)) {
+                if (j == 0) write_pair(A, p, A.theta[p], NAN, NAN, NAN, 0, RTX_RAY_BAD_INPUT);
+                p += stride;
+                continue;
+            }
+            em = emitter_of(g, e);
+            dr = mod2pi(elem_angle(g, r) - em.pe);
+            const double th0 = (dr - kPi) / 2.0;
+            link_reset(L, th0);
+            t4.n = t4.next = 0;
+            double th = th0;
+            const int st0 = A.f_st[p];
+            const FanSeed sd = A.seed[p];
+            if (sd.found) {
+                L.th = sd.th_far;
+                link_next_hit(L, sd.g_far);
+                L.th = sd.th_near;
+                th = link_next_hit(L, sd.g_near);
+                if (sd.cubic) th = sd.th_first;
+                for (int q = 0; q < 4; q++)
+                    if (q < sd.n_s) top4_push(t4, sd.s_th[q], sd.s_g[q]);
+            } else if (st0 == RTX_RAY_LINKED) {
+                th = link_next_hit(L, A.f_g[p]);
+            } else if (st0 == RTX_RAY_NO_HIT) {
+                th = 0.5 * th0;
+            }
+            L.have_neg = L.have_pos = 0;  // the coarse samples do not bound the secant
+            round_start(th);
+            active = true;
+            return;
+        }
+        active = false;
+    };
+    next_pair();
+
+    while (active) {
+        if (!waiting) {
+            Ray<R> nxt;
+            StepOut<R> so = ray_step<R, COMP, INTEG, BSP>(M, C, ray, nxt, ds);
+            n_steps++;
+            const R w_start = ray.m == 0 ? ds * (R)0.5 : ds;
+            const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
+            const R pu = (nxt.uh - cx) + nxt.ul, pv = (nxt.vh - cy) + nxt.vl;
+            const bool crossed = !bad && (pu * pu + pv * pv >= R2);
+            const bool exhausted = !bad && !crossed && (ray.m + 1 >= A.max_steps);
+            if (!(bad || crossed || exhausted)) {
+                add_T<R, COMP>(ray, w_start * so.ic1);
+                nxt.Th = ray.Th;
+                nxt.Tl = ray.Tl;
+                nxt.m = ray.m + 1;
+                ray = nxt;
+            } else {
+                n_rays++;
+                int st = RTX_RAY_NO_HIT;
+                double g_mis = NAN, T = NAN, Lm = NAN;
+                if (bad) {
+                    st = RTX_RAY_BAD_INPUT;
+                } else if (crossed) {
+                    const Hit hit = intersect<R>(g, ray, nxt);
+                    const double dsp = hit.t * g.ds;
+                    const Sample<R> sq = lookup_at<R, COMP, BSP>(M, g, hit.qx, hit.qy);
+                    if (!(sq.c > (R)0)) {
+                        st = RTX_RAY_BAD_INPUT;
+                    } else {
+                        const double wm = ray.m == 0 ? 0.5 * dsp : 0.5 * (g.ds + dsp);
+                        const double acc = ((double)ray.Th + (double)ray.Tl) + wm * (double)so.ic1 +
+                                           0.5 * dsp * (double)rcp(sq.c);
+                        T = acc * g.h;
+                        Lm = (ray.m * g.ds + dsp) * g.h;
+                        g_mis = mod2pi(atan2(hit.qy, hit.qx) - em.pe) - dr;
+                        st = RTX_RAY_LINKED;
+                    }
+                }
+                s_th[lane] = mine;
+                s_g[lane] = g_mis;
+                s_T[lane] = T;
+                s_L[lane] = Lm;
+                s_st[lane] = st;
+                waiting = true;
+            }
+        }
+        compiler_fence();
+        const unsigned long long wm = __ballot(waiting);
+        if (!(waiting && ((wm >> (lane & 62)) & 3ull) == 3ull)) continue;
+        // ---- both rays of the round are in (rare, divergent, FP64) ----
+        waiting = false;
+        double ca[2], ga[2], Ta[2], La[2];
+        int sa[2];
+        for (int q = 0; q < 2; q++) {
+            ca[q] = s_th[b0 + q];
+            ga[q] = s_g[b0 + q];
+            Ta[q] = s_T[b0 + q];
+            La[q] = s_L[b0 + q];
+            sa[q] = s_st[b0 + q];
+        }
+        L.n_marches += 2;
+        bool done = true;
+        if (sa[0] == RTX_RAY_BAD_INPUT || sa[1] == RTX_RAY_BAD_INPUT) {
+            if (j == 0) write_pair(A, p, L.th0, NAN, NAN, NAN, L.n_marches, RTX_RAY_BAD_INPUT);
+        } else {
+            int lk = -1;
+            double lmiss = INFINITY;
+            for (int q = 0; q < 2; q++) {
+                if (sa[q] != RTX_RAY_LINKED) continue;
+                const double miss = fabs(ga[q]) * g.R;
+                if (miss < L.best_miss) {
+                    L.best_miss = miss;
+                    L.best_th = ca[q];
+                    L.best_T = Ta[q];
+                    L.best_L = La[q];
+                }
+                if (miss <= A.tol && miss < lmiss) {
+                    lk = q;
+                    lmiss = miss;
+                }
+            }
+            if (lk >= 0) {
+                if (j == 0) write_pair(A, p, ca[lk], Ta[lk], La[lk], lmiss, L.n_marches, RTX_RAY_LINKED);
+            } else if (L.n_marches >= 2 * A.max_marches) {  // max_marches rounds
+                if (j == 0) {
+                    if (L.best_miss < INFINITY)
+                        write_pair(A, p, L.best_th, L.best_T, L.best_L, L.best_miss, L.n_marches,
+                                   RTX_RAY_NOT_CONVERGED);
+                    else
+                        write_pair(A, p, L.th0, NAN, NAN, NAN, L.n_marches, RTX_RAY_NO_HIT);
+                }
+            } else {
+                const bool h0 = sa[0] == RTX_RAY_LINKED, h1 = sa[1] == RTX_RAY_LINKED;
+                if (h0) top4_push(t4, ca[0], ga[0]);
+                if (h1) top4_push(t4, ca[1], ga[1]);
+                double th;
+                if (h0 && h1) {
+                    const int f = fabs(ga[0]) >= fabs(ga[1]) ? 0 : 1;
+                    L.th = ca[f];
+                    link_next_hit(L, ga[f]);
+                    L.th = ca[1 - f];
+                    th = link_next_hit(L, ga[1 - f]);
+                } else if (h0 || h1) {
+                    const int q = h0 ? 0 : 1;
+                    L.th = ca[q];
+                    th = link_next_hit(L, ga[q]);
+                } else {
+                    th = L.nvalid > 0 ? 0.5 * (ca[0] + L.thb) : 0.5 * ca[0];
+                }
+                double v;
+                if ((h0 || h1) && L.n_marches <= 4 && top4_estimate(t4, L, v)) th = v;
+                L.th = th;
+                round_start(th);
+                done = false;
+            }
+        }
+        if (done) {
+            p += stride;
+            next_pair();
+        }
+    }
+    block_sum2(n_steps, n_rays, A.stats);
+}
+
 // ---------------------------------------------------------- adjoint kernel --
 
 
@@ -1275,7 +1576,6 @@ struct QRing {
     static constexpr int kLen = 16;  // entries per marching lane (32 / 64 KB per block)
 };
 
-__device__ __forceinline__ void compiler_fence() { __asm__ volatile("" ::: "memory"); }
 
 template <class R>
 __device__ __forceinline__ void q_push(QEntry<R> *ring, unsigned *qhead, unsigned *qtail, int lane, int nm,
@@ -1553,6 +1853,17 @@ __global__ void __launch_bounds__(kBlock) k_fan_seed(Geo g, const double *__rest
                 }
             }
         }
+        sd.n_s = 0;
+        for (int q = 0; q < 4; q++) sd.s_th[q] = sd.s_g[q] = 0.0;
+        if (found >= 0)
+            for (int a = found - 1; a <= found + 2; a++) {
+                if (a < 0 || a > n - 2) continue;
+                const double ga = H[a] - Dr;
+                if (!(ga == ga)) continue;
+                sd.s_th[sd.n_s] = fan_straight(g, e, a + 1);
+                sd.s_g[sd.n_s] = ga;
+                sd.n_s++;
+            }
         if (found >= 0) {
             double ga = H[found] - Dr, gb = H[found + 1] - Dr;
             int nr = fabs(ga) <= fabs(gb) ? found : found + 1;
@@ -2512,7 +2823,16 @@ int launch_fan(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
     A3.f_L = P->f_L;
     A3.f_st = P->f_st;
     (void)n;
-    return launch_trace<R, COMP, true>(P, A3, s, 1, RTX_SLOT_FAN_LINK);
+    Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
+    auto kern = P->bsp ? (P->opts.integ == RTX_RK4 ? k_link2<R, COMP, 4, true> : k_link2<R, COMP, 2, true>)
+                       : (P->opts.integ == RTX_RK4 ? k_link2<R, COMP, 4> : k_link2<R, COMP, 2>);
+    const int blocks = grid_blocks(P, kern, 2 * A3.n_pairs);
+    P->stat_blocks[1] = blocks;
+    A3.stats = P->stats + (size_t)1 * 2 * kMaxBlocks;
+    if (int rc = time_mark(P, RTX_SLOT_FAN_LINK, 0, s)) return rc;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(P->block), 0, s, M, g, A3);
+    HIP_TRY(hipGetLastError());
+    return time_mark(P, RTX_SLOT_FAN_LINK, 1, s);
 }
 
 template <class R, bool COMP>
