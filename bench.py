@@ -82,7 +82,7 @@ def run_gpu(prec, c_host, cfg, steps, warmup, resid_host, fan=True):
         "forward_ms": fwd_ms,
         "adjoint_ms": avg["adjoint"],
         "forward_rays_per_s": n / (fwd_ms * 1e-3),
-        "dominant_kernel": "linking pass (k_trace, fan-seeded)" if fan else "k_trace",
+        "dominant_kernel": "linking pass (k_link2, fan-seeded, two lanes per pair)" if fan else "k_trace",
         "dominant_ms": avg["fan_link"] if fan else avg["trace"],
         "dominant_rk_steps": int(link_steps),
         "trace_rk_steps": int(trace_steps),
@@ -224,7 +224,7 @@ def measured_traffic(_unused=None):
         if d.get("source_sha256") != sha:
             continue
         for name, v in d.get("kernels", {}).items():
-            if name.startswith("k_trace<float, true, 4, false, true, false>"):  # the fan-seeded linking pass
+            if name.startswith("k_link2<float, true, 4, false>"):  # the fan-seeded linking pass
                 return v["fetch_bytes"] + v["write_bytes"]
     return None
 
@@ -278,7 +278,7 @@ def main():
             "frac": flops / t_s / 1e12 / PEAK_FP32_NONPACKED_TFLOPS, "traffic": None,
             "frac_vs_published_157": flops / t_s / 1e12 / PEAK_FP32_TFLOPS}
     gbytes = f32["dominant_rk_steps"] * GATHER_VALUES_PER_STEP * 4
-    gather = {"kernel": "k_trace<float> linking pass", "bytes_per_launch": gbytes,
+    gather = {"kernel": "k_link2<float> linking pass", "bytes_per_launch": gbytes,
               "achieved_GBs": gbytes / t_s / 1e9, "vs_hbm_peak_frac": gbytes / t_s / 1e9 / PEAK_HBM_GBS}
 
     roof["traffic"] = measured_traffic()
