@@ -251,6 +251,10 @@ int rtx_march_free(rtx_plan plan, const double *c, int64_t n_rays, const double 
    whose theta is a traced ray that reached the ring; others are skipped.  grad: [ny][nx] float (RTX_F32C) or double
    (RTX_F64), accumulated into (the caller zeroes it).  Accumulation uses
    atomics, so the FP32 result depends on summation order at rounding level.
+   The updates first go to zeroed copies of the grid that the plan allocates on
+   its first adjoint call (as many as fit in 64 MiB, at most 8; with room for
+   fewer than two they go to grad directly), and a final kernel adds the copies
+   into grad and zeroes them again.
    Node updates pass through a bounded queue in on-chip memory; if one of its
    waits ever hits its bound, the gradient is incomplete and the next
    rtx_plan_stats call on the plan returns RTX_E_HIP. */

@@ -167,6 +167,32 @@ def test_adjoint_matches_oracle(rtx, prec, weight):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_adjoint_accumulates_across_calls(rtx, prec):
+    """grad is added into, call after call: the plan's zeroed gradient copies
+    (one per group of blocks) are summed into grad and left zeroed, so a second
+    call with rho and a third with -2 rho bring grad back to 0 + rho - 2 rho +
+    rho = 0 up to rounding, and an explicit pair list (queue path, same copies)
+    gives the all-pairs result."""
+    n, h = 96, 0.5e-3
+    c = _gauss(n, h, seed=9)
+    ring = (32, 0.45 * n * h * 0.9, 0.0)
+    pairs = synth.all_pairs(32)
+    ref = oracle.trace(oracle.grid_medium(c, h), ring, pairs)
+    rho = synth.real_residual(len(pairs), 2003)
+    plan = rtx.Plan(n, n, h, *ring, prec=prec)
+    th, st = _dev(ref["theta"]), _dev(ref["status"])
+    g1 = _np(plan.adjoint(th, st, _dev(rho), c=_dev(c))).astype(np.float64)
+    g = plan.adjoint(th, st, _dev(rho))
+    g = plan.adjoint(th, st, _dev(-2.0 * rho), grad=g)
+    g = plan.adjoint(th, st, _dev(rho), grad=g)
+    scale = np.abs(g1).max()
+    assert np.abs(_np(g).astype(np.float64)).max() < (1e-12 if prec == "f64" else 1e-5) * scale
+    gp = _np(plan.adjoint(th, st, _dev(rho), pairs=_dev(pairs))).astype(np.float64)
+    plan.close()
+    assert np.abs(gp - g1).max() < (1e-12 if prec == "f64" else 1e-5) * scale
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
 def test_rayborn_adjoint_matches_oracle(rtx, prec):
     n, h = 96, 0.5e-3
     c = _gauss(n, h, seed=12)
