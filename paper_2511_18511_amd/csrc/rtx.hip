@@ -1614,39 +1614,115 @@ __device__ __forceinline__ void q_push(QEntry<R> *ring, unsigned *qhead, unsigne
     __hip_atomic_store(qhead + lane, head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The drain wave merges node updates in a direct-mapped cache in LDS (its own;
+// no other wave touches it) before they reach the grid: the rays of a block
+// run side by side through one band of the grid, so an update usually finds
+// its node in the cache, and the grid sees one float atomic per eviction and
+// per cached node at the end instead of one per update (on the 256x256
+// workload a 16 x 16 tile's ~140k updates touch 5k-11k nodes).  An update
+// whose node holds its slot adds to it with an LDS atomic.  A missing node
+// claims the slot: each such lane writes a tag (lane, ring) to the slot's
+// claim word and reads it back, and the lane whose tag stayed adds the slot's
+// old node to the grid and takes the slot; the others add to the grid
+// directly.  LDS operations of the wave take effect in program order, so a
+// read-back sees every lane's earlier write and every earlier LDS add.
+template <class R>
+struct NodeCache {
+    static constexpr int kBits = sizeof(R) == 4 ? 13 : 12;  // 96 / 64 KB with the claim words
+    static constexpr int kSlots = 1 << kBits;
+};
+constexpr unsigned kCacheEmpty = 0xffffffffu;  // node values stay below it (2^24 nodes, 255 instances)
+
+__device__ __forceinline__ unsigned cache_slot(unsigned node, int bits)
+{
+    return (node * 0x9E3779B1u) >> (32 - bits);
+}
+
+template <class R, bool BATCH>
+__device__ __forceinline__ void grid_add(R *grad, const BatchArgs &B, unsigned node, R v)
+{
+    R *g = grad;
+    if (BATCH) {
+        g = ((const Inst<R> *)B.inst)[node >> 24].grad;
+        node &= 0xffffffu;
+    }
+    unsafeAtomicAdd(g + node, v);
+}
+
 // The last wave of a block drains the rings of marching lanes lane, lane + 64,
-// ... into the grid until every one of them is marked done and empty.
+// ... (one entry per ring and pass) through the cache until every ring is
+// marked done and empty, then adds the cached nodes to the grid.
 template <class R, bool BATCH>
 __device__ __forceinline__ void q_drain(const QEntry<R> *ring, const unsigned *qhead, unsigned *qtail, int nm,
-                                        R *grad, const BatchArgs &B, unsigned *err)
+                                        R *grad, const BatchArgs &B, unsigned *err, unsigned *c_claim,
+                                        unsigned *c_key, R *c_val)
 {
     constexpr unsigned len = QRing<R>::kLen;
+    constexpr int NJ = kBlock / 64;
+    constexpr int kBits = NodeCache<R>::kBits;
     const int lane = threadIdx.x - nm;
-    unsigned tl[kBlock / 64] = {};
+    for (int i = lane; i < NodeCache<R>::kSlots; i += 64) c_key[i] = kCacheEmpty;
+    unsigned tl[NJ] = {};
     for (unsigned idle = 0;;) {
         bool done = true, moved = false;
-        for (int j = 0; j < kBlock / 64; j++) {
-            if (j * 64 >= nm) break;
-            const int pl = lane + 64 * j;
-            const unsigned h = __hip_atomic_load(qhead + pl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            compiler_fence();
-            const unsigned hh = h & ~kQDone;
-            while (tl[j] != hh) {
-                const QEntry<R> q = ring[(tl[j] & (len - 1)) * nm + pl];
-                R *g = grad;
-                unsigned node = q.node;
-                if (BATCH) {
-                    g = ((const Inst<R> *)B.inst)[node >> 24].grad;
-                    node &= 0xffffffu;
-                }
-                unsafeAtomicAdd(g + node, q.val);
+        unsigned h[NJ];
+        for (int j = 0; j < NJ; j++)
+            h[j] = j * 64 < nm ? __hip_atomic_load(qhead + lane + 64 * j, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP)
+                               : kQDone;
+        compiler_fence();
+        QEntry<R> q[NJ];
+        bool have[NJ];
+        for (int j = 0; j < NJ; j++) {
+            have[j] = tl[j] != (h[j] & ~kQDone);
+            // (read for every ring of this block, in bounds: (len - 1) nm + pl < len kBlock)
+            if (j * 64 < nm) q[j] = ring[(tl[j] & (len - 1)) * nm + lane + 64 * j];
+        }
+        for (int j = 0; j < NJ; j++)
+            if (have[j]) {
                 tl[j]++;
                 moved = true;
             }
-            compiler_fence();
-            __hip_atomic_store(qtail + pl, tl[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            done = done && (h & kQDone);
+        compiler_fence();
+        for (int j = 0; j < NJ; j++) {
+            if (j * 64 < nm)
+                __hip_atomic_store(qtail + lane + 64 * j, tl[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            done = done && (h[j] & kQDone) && tl[j] == (h[j] & ~kQDone);
         }
+        // (plain LDS accesses between compiler barriers, which make the compiler
+        // re-read what other lanes may have written; loads are issued for every
+        // j, unused ones at slot 0, so that each phase's loads go out together)
+        unsigned slot[NJ], key[NJ];
+        for (int j = 0; j < NJ; j++) slot[j] = have[j] ? cache_slot(q[j].node, kBits) : 0u;
+        for (int j = 0; j < NJ; j++) key[j] = c_key[slot[j]];
+        // hits add in LDS (atomically: lanes of one instruction may share a node)
+        bool miss[NJ];
+        for (int j = 0; j < NJ; j++) {
+            miss[j] = have[j] && key[j] != q[j].node;
+            if (have[j] && !miss[j]) atomicAdd(c_val + slot[j], q[j].val);
+            if (miss[j]) c_claim[slot[j]] = (unsigned)(lane * NJ + j);
+        }
+        compiler_fence();
+        unsigned tag[NJ];
+        R old[NJ];
+        for (int j = 0; j < NJ; j++) {
+            tag[j] = c_claim[slot[j]];
+            old[j] = c_val[slot[j]];
+        }
+        compiler_fence();
+        // a miss whose claim stayed evicts the slot's node and takes the slot;
+        // the other misses go to the grid
+        for (int j = 0; j < NJ; j++) {
+            if (!miss[j]) continue;
+            if (tag[j] == (unsigned)(lane * NJ + j)) {
+                if (key[j] != kCacheEmpty) grid_add<R, BATCH>(grad, B, key[j], old[j]);
+                c_key[slot[j]] = q[j].node;
+                c_val[slot[j]] = q[j].val;
+            } else {
+                grid_add<R, BATCH>(grad, B, q[j].node, q[j].val);
+            }
+        }
+        compiler_fence();
         if (__all(done)) break;
         if (!__any(moved)) {
             if (++idle > kQSpin) {
@@ -1655,6 +1731,10 @@ __device__ __forceinline__ void q_drain(const QEntry<R> *ring, const unsigned *q
             }
             __builtin_amdgcn_s_sleep(2);
         }
+    }
+    for (int i = lane; i < NodeCache<R>::kSlots; i += 64) {
+        const unsigned k = c_key[i];
+        if (k != kCacheEmpty) grid_add<R, BATCH>(grad, B, k, c_val[i]);
     }
 }
 
@@ -1726,11 +1806,13 @@ __global__ void __launch_bounds__(kBlock + kFlushLanes) k_adjoint(Medium<R> M, G
     if (!BATCH) grad += (size_t)(blockIdx.x % A.n_copies) * M.nx * M.ny;
     __shared__ QEntry<R> q_ring[QRing<R>::kLen * kBlock];
     __shared__ unsigned q_head[kBlock], q_tail[kBlock];
+    __shared__ unsigned c_claim[NodeCache<R>::kSlots], c_key[NodeCache<R>::kSlots];
+    __shared__ R c_val[NodeCache<R>::kSlots];
     const int nm = (int)blockDim.x - kFlushLanes;
     for (int i = threadIdx.x; i < nm; i += blockDim.x) q_head[i] = q_tail[i] = 0;
     __syncthreads();
     if ((int)threadIdx.x >= nm) {
-        q_drain<R, BATCH>(q_ring, q_head, q_tail, nm, grad, B, A.err);
+        q_drain<R, BATCH>(q_ring, q_head, q_tail, nm, grad, B, A.err, c_claim, c_key, c_val);
         block_sum2(0ull, 0ull, A.stats);
         return;
     }
