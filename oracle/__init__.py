@@ -65,6 +65,7 @@ def _load(path):
                                         C.c_int, C.c_int, C.c_double, _dp, C.c_int, _dp, _dp]
     L.or_march_free.argtypes = med + [C.c_int, C.c_double, _dp, _dp, C.c_int, _dp]
     L.or_fan_cubic.argtypes = [_dp, _dp, C.c_int, C.c_int, _dp]
+    L.or_fan_quintic.argtypes = [_dp, _dp, C.c_int, C.c_int, _dp]
     L.or_interp.argtypes = med + [C.c_int, _dp, _dp, _dp, _dp]
     L.or_weights_row.argtypes = [C.c_int, C.c_int, C.c_double, _dp, C.c_int, C.c_double, C.c_double,
                                  C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double, _ip, _dp,
@@ -274,6 +275,16 @@ def fan_cubic(G, TH, a):
     TH = np.ascontiguousarray(TH, dtype=np.float64)
     out = np.zeros(1)
     ok = lib().or_fan_cubic(_d(G), _d(TH), len(G), int(a), _d(out))
+    return float(out[0]) if ok else None
+
+
+def fan_quintic(G, TH, a):
+    """Quintic estimate of a fan seed with bracket (a, a+1) from the samples
+    a-2..a+3 (the first round's second ray): the angle, or None."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    TH = np.ascontiguousarray(TH, dtype=np.float64)
+    out = np.zeros(1)
+    ok = lib().or_fan_quintic(_d(G), _d(TH), len(G), int(a), _d(out))
     return float(out[0]) if ok else None
 
 

@@ -645,6 +645,33 @@ static int fan_cubic(const double *G, const double *TH, int m, int a, double *th
     return 1;
 }
 
+/* Quintic refinement of the fan seed, the second ray of the first round: with
+   the bracket (a, a+1) and two samples on each side of it sampled and G strictly
+   monotone over the six samples a-2..a+3, the value at G = 0 of the quintic
+   that interpolates theta as a function of G through them, if it lies strictly
+   inside the bracket (returns 1); otherwise 0. */
+static int fan_quintic(const double *G, const double *TH, int m, int a, double *th)
+{
+    if (a < 2 || a + 3 > m - 1) return 0;
+    const double *g = G + a - 2, *t = TH + a - 2;
+    for (int i = 0; i < 6; i++)
+        if (!(g[i] == g[i])) return 0;
+    int up = g[1] > g[0];
+    for (int i = 0; i < 5; i++)
+        if (up ? !(g[i + 1] > g[i]) : !(g[i + 1] < g[i])) return 0;
+    double v = 0.0;
+    for (int i = 0; i < 6; i++) {
+        double w = 1.0;
+        for (int l = 0; l < 6; l++)
+            if (l != i) w *= (0.0 - g[l]) / (g[i] - g[l]);
+        v += w * t[i];
+    }
+    double lo = t[2] < t[3] ? t[2] : t[3], hi = t[2] < t[3] ? t[3] : t[2];
+    if (!(v > lo && v < hi)) return 0;
+    *th = v;
+    return 1;
+}
+
 /* The four samples of smallest |g| seen by a fan-started pair: its fan seed
  * samples (bracket and outer neighbours, in order) and then every hitting ray
  * it traced (round by round, ray 0 first).  A new sample replaces the kept one
@@ -722,7 +749,10 @@ static int top4_estimate(const Top4 *t, const LinkState *s, double *th)
  * the primary angle c0 and a hedge c1 = c0 - (c0 - ref) / 10, a tenth of the way
  * back towards the latest fed sample ref (or the start angle), so that a round
  * that does not link leaves two close samples, i.e. a local derivative, for the
- * next secant step.  After a round: a ray with bad input ends the pair (BAD);
+ * next secant step; in the first round the hedge is the fan seed's quintic
+ * estimate instead (fan_quintic; have_q), when there is one and it differs
+ * from c0: the cubic and the quintic interpolant bracket most of the seed's
+ * interpolation error between them.  After a round: a ray with bad input ends the pair (BAD);
  * every hitting ray enters the best-ray record (ray 0 first); the hitting ray of
  * smallest miss within the tolerance is the result; after max_marches rounds
  * (2 max_marches rays: the rounds, not the rays, are sequential) the best ray
@@ -735,12 +765,13 @@ static int top4_estimate(const Top4 *t, const LinkState *s, double *th)
  * keep the safeguarded secant alone, whose bracket halving does not stall on a
  * misfit that jumps).  Both rays count as traced rays. */
 static void link_pairs(const Medium *m, const Ring *ring, const Opts *o, int e, int rcv, LinkState *s, Top4 *t4,
-                       double th, LinkOut *out)
+                       double th, int have_q, double thq, LinkOut *out)
 {
     out->n_marches = 0;
     for (;;) {
         double ref = s->nvalid > 0 ? s->thb : s->th0;
         double c[2] = {th, th == ref ? th + 1e-4 : th - 0.1 * (th - ref)};
+        if (out->n_marches == 0 && have_q && thq != th) c[1] = thq;
         double g[2], T[2], L[2];
         int st[2];
         for (int j = 0; j < 2; j++) st[j] = trace_at(m, ring, o, e, rcv, c[j], &g[j], &T[j], &L[j], NULL);
@@ -822,7 +853,8 @@ static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, in
         G[j - 1] = row[j - 1].st == ST_LINKED ? (row[j - 1].g + Dj) - Dr : NAN;
         TH[j - 1] = straight_angle(ring, e, k);
     }
-    int found = -1;
+    int found = -1, have_q = 0;
+    double thq = 0.0;
     for (int d = 0; d < n && found < 0; d++) {
         int cand[2] = {jr - 1 + d, jr - 1 - d - 1};
         for (int c = 0; c < 2; c++) {
@@ -842,6 +874,7 @@ static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, in
         th = link_after_hit(&s, TH[near], G[near]);
         double thc;
         if (fan_cubic(G, TH, n - 1, found, &thc)) th = thc;
+        have_q = fan_quintic(G, TH, n - 1, found, &thq);
         for (int i = found - 1; i <= found + 2; i++)
             if (i >= 0 && i <= n - 2 && G[i] == G[i]) top4_push(&t4, TH[i], G[i]);
     } else if (own->st == ST_LINKED) {
@@ -856,7 +889,7 @@ static void link_fan(const Medium *m, const Ring *ring, const Opts *o, int e, in
     s.have_neg = s.have_pos = 0;
     free(G);
     free(TH);
-    link_pairs(m, ring, o, e, rcv, &s, &t4, th, out);
+    link_pairs(m, ring, o, e, rcv, &s, &t4, th, have_q, thq, out);
 }
 
 /* Step of the fan rays: four times the tracing step, at most one pixel (and
@@ -1202,6 +1235,12 @@ int or_rayborn_rho(int n, int n_freq, const double *T, const double *freqs, cons
 int or_fan_cubic(const double *G, const double *TH, int m, int a, double *th)
 {
     return fan_cubic(G, TH, m, a, th);
+}
+
+/* The first round's quintic hedge on its own (same arguments). */
+int or_fan_quintic(const double *G, const double *TH, int m, int a, double *th)
+{
+    return fan_quintic(G, TH, m, a, th);
 }
 
 /* SART, the default solver of the linearised ToF subproblem (Sec. 3.1; the

@@ -47,6 +47,12 @@ MUTATIONS = {
                                   "const double *g = G + a - 1, *t = TH + a;"),
     "fan_cubic_bracket_ends": ("double lo = t[1] < t[2] ? t[1] : t[2], hi = t[1] < t[2] ? t[2] : t[1];",
                                "double lo = t[0] < t[3] ? t[0] : t[3], hi = t[0] < t[3] ? t[3] : t[0];"),
+    "fan_quintic_weight_sign": ("if (l != i) w *= (0.0 - g[l]) / (g[i] - g[l]);",
+                                "if (l != i) w *= (0.0 + g[l]) / (g[i] - g[l]);"),
+    "fan_quintic_shifted_stencil": ("const double *g = G + a - 2, *t = TH + a - 2;",
+                                    "const double *g = G + a - 2, *t = TH + a - 1;"),
+    "fan_quintic_hedge_dropped": ("if (out->n_marches == 0 && have_q && thq != th) c[1] = thq;",
+                                  "if (out->n_marches == 0 && have_q && thq != th) c[1] = c[1];"),
     "sart_rowsum_dropped": ("double r = (b[i] - proj) / M[i];", "double r = (b[i] - proj);"),
     "sart_colsum_dropped": ("if (V[j] != 0.0) x[j] += lambda * upd[j] / V[j];",
                             "if (V[j] != 0.0) x[j] += lambda * upd[j];"),
@@ -86,6 +92,10 @@ PINS = [
     lambda o: P.test_fan_cubic_exact_for_cubic_inverse(o),
     lambda o: P.test_fan_cubic_fourth_order_on_smooth_inverse(o),
     lambda o: P.test_fan_cubic_falls_back(o),
+    lambda o: P.test_fan_quintic_exact_for_quintic_inverse(o),
+    lambda o: P.test_fan_quintic_sixth_order_on_smooth_inverse(o),
+    lambda o: P.test_fan_quintic_falls_back(o),
+    lambda o: P.test_fan_first_round_traces_the_quintic(o),
     lambda o: P.test_fan_start_same_roots_fewer_rays(o),
     lambda o: P.test_fan_start_fisheye_reversed_orientation(o),
     lambda o: P.test_paraxial_homogeneous_closed_form(o, "rk4"),

@@ -567,6 +567,96 @@ def test_fan_cubic_falls_back(orc):
     assert r is None or TH[2] < r < TH[3]
 
 
+# ---------------------------------------------- fan start: quintic hedge --
+def test_fan_quintic_exact_for_quintic_inverse(orc):
+    """When theta is a quintic polynomial of G, the first round's second angle
+    is its value at G = 0 (inverse interpolation through six samples is then
+    exact), for increasing and decreasing samples."""
+    p = np.array([0.013, -0.7, 0.4, 2.5, -3.0, 6.0])
+    G = np.array([-0.3, -0.21, -0.12, -0.05, 0.03, 0.11, 0.2, 0.28])
+    TH = sum(p[k] * G ** k for k in range(6))
+    a = 3  # bracket (G[3] < 0 < G[4])
+    th = orc.fan_quintic(G, TH, a)
+    assert th is not None and abs(th - p[0]) < 1e-15
+    th2 = orc.fan_quintic(G[::-1], TH[::-1], len(G) - 2 - a)
+    assert th2 is not None and abs(th2 - p[0]) < 1e-15
+    # the cubic through the middle four is not exact here
+    assert abs(orc.fan_cubic(G, TH, a) - p[0]) > 1e-6
+
+
+def test_fan_quintic_sixth_order_on_smooth_inverse(orc):
+    """G(theta) = tan(theta - 0.1) + 0.3 (theta - 0.1)^2 on a uniform fan of
+    spacing d: the quintic's error falls at least as d^6 (about d^6.7 on this
+    function over these spacings), the cubic's as d^4, and the quintic is far
+    more accurate."""
+    root = 0.1
+
+    def G(t):
+        return np.tan(t - root) + 0.3 * (t - root) ** 2
+
+    errs, errs_c = [], []
+    for d in (0.04, 0.02, 0.01):
+        TH = root - 0.37 * d + d * np.arange(-3, 5)  # root inside the bracket (3, 4)
+        errs.append(abs(orc.fan_quintic(G(TH), TH, 3) - root))
+        errs_c.append(abs(orc.fan_cubic(G(TH), TH, 3) - root))
+    for k in range(2):
+        assert 60 < errs[k] / errs[k + 1] < 200, errs
+    assert errs[-1] < 1e-4 * errs_c[-1]
+
+
+def test_fan_quintic_falls_back(orc):
+    TH = np.linspace(-0.1, 0.1, 8)
+    good = np.array([-0.45, -0.3, -0.2, -0.05, 0.06, 0.2, 0.31, 0.44])
+    assert orc.fan_quintic(good, TH, 3) is not None
+    assert orc.fan_quintic(good, TH, 1) is None  # one sample below the bracket
+    assert orc.fan_quintic(good, TH, 5) is None  # one above
+    bump = good.copy()
+    bump[2] = -0.35  # not monotone over samples 1..6
+    assert orc.fan_quintic(bump, TH, 3) is None
+    nan = good.copy()
+    nan[6] = np.nan  # an outer ray that did not hit
+    assert orc.fan_quintic(nan, TH, 3) is None
+
+
+def test_fan_first_round_traces_the_quintic(orc):
+    """The first round's second ray is the quintic estimate from the pair's fan
+    samples: some pairs of a Gaussian-inclusion medium link in one round at
+    exactly that angle, away from the cubic one (samples recomputed here from
+    coarse rays at the fan's step: four tracing steps)."""
+    n, h = 96, 0.5e-3
+    c = synth.gaussian_inclusions(n, n, h, seed=21, r_max=0.7 * 0.45 * n * h)
+    n_el = 32
+    ring = (n_el, 0.45 * n * h * 0.9, 0.0)
+    pairs = synth.all_pairs(n_el)
+    med = orc.grid_medium(c, h)
+    o = orc.trace(med, ring, pairs, fan=True)
+    two_pi = 2 * np.pi
+    phi = lambda k: two_pi * k / n_el  # noqa: E731
+    n_quintic = 0
+    for e in range(0, n_el, 3):
+        TH = np.array([((phi((e + j) % n_el) - phi(e)) % two_pi - np.pi) / 2 for j in range(1, n_el)])
+        Hj = np.full(n_el - 1, np.nan)
+        for j in range(1, n_el):
+            k = (e + j) % n_el
+            _, _, g = orc.march_points(med, ring, e, k, TH[j - 1], ds_px=1.0)
+            Hj[j - 1] = g + (phi(k) - phi(e)) % two_pi
+        for r in range(n_el):
+            if r == e:
+                continue
+            i = e * (n_el - 1) + (r if r < e else r - 1)
+            if o["n_marches"][i] != 2 or o["status"][i] != orc.LINKED:
+                continue
+            G = Hj - (phi(r) - phi(e)) % two_pi
+            jr = (r - e) % n_el
+            a = next((b for d in range(n_el) for b in (jr - 1 + d, jr - 2 - d)
+                      if 0 <= b <= n_el - 3 and G[b] * G[b + 1] <= 0), None)
+            q = None if a is None else orc.fan_quintic(G, TH, a)
+            cub = None if a is None else orc.fan_cubic(G, TH, a)
+            if q is not None and cub is not None and abs(q - cub) > 1e-9 and abs(o["theta"][i] - q) < 1e-12:
+                n_quintic += 1
+    assert n_quintic >= 3, n_quintic
+
+
 # ---------------------------------------------------------------- SART ------
 def _csr(W):
     rowptr = np.zeros(W.shape[0] + 1, np.int64)
