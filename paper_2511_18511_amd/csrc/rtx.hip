@@ -889,8 +889,9 @@ __device__ __forceinline__ bool top4_estimate(const Top4 &t, const Link &L, doub
 struct FanSeed {
     double th_far, g_far, th_near, g_near;  // bracket ends (larger |g| first)
     double th_first;                        // first linking angle (cubic), if `cubic`
+    double th_q;                            // the first round's second angle (quintic), if `quintic`
     double s_th[4], s_g[4];                 // the bracket and its outer neighbours that hit, in order
-    int found, cubic, n_s;
+    int found, cubic, quintic, n_s;
 };
 
 constexpr uint32_t kStraight = 1u << 16;  // internal: fixed pass at straight angles
@@ -1073,7 +1074,7 @@ __device__ __forceinline__ void mark_done(const BatchArgs &B, int k)
     if (atomicSub(B.remain + k, 1u) == 1u) B.t_done[k] = wall_clock64();
 }
 
-template <class R, bool COMP, int INTEG, bool BATCH, bool FAN = false, bool BSP = false>
+template <class R, bool COMP, int INTEG, bool BATCH, bool BSP = false>
 __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs A, BatchArgs B)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1119,25 +1120,6 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
                 double th0 = given ? a.theta[q] : (dr - kPi) / 2.0;
                 link_reset(L, th0);
                 double th = th0;
-                if (FAN) {
-                    // the coarse fan rays (a seed only, not counted) bracket the
-                    // root; every ray of the pair is traced here
-                    const int st0 = a.f_st[q];
-                    const FanSeed sd = a.seed[q];
-                    if (sd.found) {
-                        L.th = sd.th_far;
-                        link_next_hit(L, sd.g_far);
-                        L.th = sd.th_near;
-                        th = link_next_hit(L, sd.g_near);
-                        if (sd.cubic) th = sd.th_first;
-                    } else if (st0 == RTX_RAY_LINKED) {
-                        th = link_next_hit(L, a.f_g[q]);
-                    } else if (st0 == RTX_RAY_NO_HIT) {
-                        th = 0.5 * th0;
-                    }
-                    L.th = th;
-                    L.have_neg = L.have_pos = 0;  // the coarse samples do not bound the secant
-                }
                 start_ray<R, COMP>(ray, gg, em, th);
                 if (!BSP) slots_prime(m, C, ray, ds, INTEG);
                 active = true;
@@ -1245,7 +1227,10 @@ __global__ void __launch_bounds__(kBlock) k_trace(Medium<R> M, Geo g, TraceArgs 
 // and keep identical copies of its linking state; each round lane 0 traces the
 // primary angle c0 and lane 1 the hedge c1 = c0 - (c0 - ref) / 10 (ref: the
 // latest fed sample, or the start angle), a tenth of the way back, so that a
-// round that does not link leaves two close samples for the next step.  A lane
+// round that does not link leaves two close samples for the next step; in the
+// first round lane 1 traces the fan seed's quintic estimate instead, when there
+// is one and it differs from c0 (the seed's miss is mostly the cubic's
+// interpolation error, and the quintic removes about half of the second rounds).  A lane
 // whose ray ends posts its result to LDS and idles; when both have posted (a
 // wave ballot), both read the two results and take the same decision:
 //   bad input -> BAD; every hitting ray enters the best record (ray 0 first);
@@ -1286,9 +1271,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     double mine = 0;
     bool active = false, waiting = false;
 
-    auto round_start = [&](double th) {
+    auto round_start = [&](double th, bool use_q, double th_q) {
         const double ref = L.nvalid > 0 ? L.thb : L.th0;
-        mine = j == 0 ? th : (th == ref ? th + 1e-4 : th - 0.1 * (th - ref));
+        mine = j == 0 ? th : (use_q && th_q != th ? th_q : th == ref ? th + 1e-4 : th - 0.1 * (th - ref));
         start_ray<R, COMP>(ray, g, em, mine);
         if (!BSP) slots_prime(M, C, ray, ds, INTEG);
     };
@@ -1321,7 +1306,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
                 th = 0.5 * th0;
             }
             L.have_neg = L.have_pos = 0;  // the coarse samples do not bound the secant
-            round_start(th);
+            round_start(th, sd.found && sd.quintic, sd.th_q);
             active = true;
             return;
         }
@@ -1441,7 +1426,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
                 double v;
                 if ((h0 || h1) && L.n_marches <= 4 && top4_estimate(t4, L, v)) th = v;
                 L.th = th;
-                round_start(th);
+                round_start(th, false, 0.0);
                 done = false;
             }
         }
@@ -1923,6 +1908,41 @@ __device__ __forceinline__ double fan_straight(const Geo &g, int e, int j)
     return (mod2pi(elem_angle(g, k) - elem_angle(g, e)) - kPi) / 2.0;
 }
 
+// Zero of the polynomial interpolating theta as a function of G = H - Dr through
+// the 2 HW fan samples around the bracket (found, found + 1): HW = 2 gives the
+// cubic first angle, HW = 3 the quintic second angle of the first round.  All
+// samples must exist, hit, be strictly monotone in G, and the zero must lie
+// strictly inside the bracket.
+template <int HW>
+__device__ __forceinline__ bool fan_inverse(const Geo &g, int e, const double *H, double Dr, int n, int found,
+                                            double &th)
+{
+    constexpr int NP = 2 * HW;
+    const int lo_i = found - (HW - 1);
+    if (lo_i < 0 || found + HW > n - 2) return false;
+    double gg[NP], tt[NP];
+    bool ok = true;
+    for (int q = 0; q < NP; q++) {
+        gg[q] = H[lo_i + q] - Dr;
+        tt[q] = fan_straight(g, e, lo_i + q + 1);  // the sample at index a is the ray at offset a + 1
+        ok = ok && gg[q] == gg[q];
+    }
+    const bool up = gg[1] > gg[0];
+    for (int q = 0; q < NP - 1; q++) ok = ok && (up ? gg[q + 1] > gg[q] : gg[q + 1] < gg[q]);
+    if (!ok) return false;
+    double v = 0.0;
+    for (int q = 0; q < NP; q++) {
+        double w = 1.0;
+        for (int m = 0; m < NP; m++)
+            if (m != q) w *= (0.0 - gg[m]) / (gg[q] - gg[m]);
+        v += w * tt[q];
+    }
+    const double lo = fmin(tt[HW - 1], tt[HW]), hi = fmax(tt[HW - 1], tt[HW]);
+    if (!(v > lo && v < hi)) return false;
+    th = v;
+    return true;
+}
+
 __global__ void __launch_bounds__(kBlock) k_fan_seed(Geo g, const double *__restrict__ f_g,
                                                      const int8_t *__restrict__ f_st, FanSeed *__restrict__ seed)
 {
@@ -1955,33 +1975,9 @@ __global__ void __launch_bounds__(kBlock) k_fan_seed(Geo g, const double *__rest
         }
         FanSeed sd;
         sd.found = found >= 0;
-        sd.cubic = 0;
-        sd.th_far = sd.g_far = sd.th_near = sd.g_near = sd.th_first = 0.0;
-        if (found >= 1 && found + 2 <= n - 2) {
-            double gg[4], tt[4];
-            bool ok = true;
-            for (int q = 0; q < 4; q++) {
-                gg[q] = H[found - 1 + q] - Dr;
-                tt[q] = fan_straight(g, e, found + q);  // offset (found - 1 + q) + 1
-                ok = ok && gg[q] == gg[q];
-            }
-            const bool up = gg[1] > gg[0];
-            for (int q = 0; q < 3; q++) ok = ok && (up ? gg[q + 1] > gg[q] : gg[q + 1] < gg[q]);
-            if (ok) {
-                double v = 0.0;
-                for (int q = 0; q < 4; q++) {
-                    double w = 1.0;
-                    for (int m = 0; m < 4; m++)
-                        if (m != q) w *= (0.0 - gg[m]) / (gg[q] - gg[m]);
-                    v += w * tt[q];
-                }
-                const double lo = fmin(tt[1], tt[2]), hi = fmax(tt[1], tt[2]);
-                if (v > lo && v < hi) {
-                    sd.cubic = 1;
-                    sd.th_first = v;
-                }
-            }
-        }
+        sd.th_far = sd.g_far = sd.th_near = sd.g_near = sd.th_first = sd.th_q = 0.0;
+        sd.cubic = found >= 0 && fan_inverse<2>(g, e, H, Dr, n, found, sd.th_first);
+        sd.quintic = found >= 0 && fan_inverse<3>(g, e, H, Dr, n, found, sd.th_q);
         sd.n_s = 0;
         for (int q = 0; q < 4; q++) sd.s_th[q] = sd.s_g[q] = 0.0;
         if (found >= 0)
@@ -2893,16 +2889,16 @@ int grid_blocks(const rtx_plan_s *P, K kernel, int64_t n)
     return grid_blocks_for(P->n_cu, P->block, kernel, n);
 }
 
-template <class R, bool COMP, bool FAN = false>
+template <class R, bool COMP>
 int launch_trace(rtx_plan_s *P, const TraceArgs &A, hipStream_t s, int region = 0, int slot = RTX_SLOT_TRACE,
                  double ds_px = 0.0)
 {
     Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
     Geo g = make_geo(P);
     if (ds_px > 0.0) g.ds = ds_px;
-    auto kern = P->bsp ? (P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false, FAN, true>
-                                                   : k_trace<R, COMP, 2, false, FAN, true>)
-                       : (P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false, FAN> : k_trace<R, COMP, 2, false, FAN>);
+    auto kern = P->bsp ? (P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false, true>
+                                                   : k_trace<R, COMP, 2, false, true>)
+                       : (P->opts.integ == RTX_RK4 ? k_trace<R, COMP, 4, false> : k_trace<R, COMP, 2, false>);
     int blocks = grid_blocks(P, kern, A.n_pairs);
     P->stat_blocks[region] = blocks;
     BatchArgs B{};
