@@ -78,10 +78,18 @@ enum rtx_flags {
     RTX_FIXED_ANGLE = 2u, /* trace once at the given theta, no linking */
     RTX_FAN_START = 4u,   /* cold start seeded from the emitter's fan of straight rays
                              (all ordered pairs only, pairs == NULL): every pair's
-                             straight ray is traced first (its first traced ray);
-                             the nearest sign change of the misfit over rays of
-                             neighbouring receivers of the same emitter seeds the
-                             secant; the linking rules are unchanged */
+                             straight ray is first traced at a coarser step (a
+                             seed, not counted); the nearest sign change of the
+                             misfit over the rays of neighbouring receivers of
+                             the same emitter seeds the secant, with a cubic
+                             (first ray) and a quintic (second ray) inverse
+                             interpolation of the fan samples; the linking then
+                             runs in rounds of two rays (n_marches counts rays,
+                             max_marches bounds the rounds).  The plan keeps a
+                             mid-path checkpoint of every pair's linked ray
+                             (2 x (44 or 84) + 16 bytes per pair of max_pairs),
+                             which the all-pairs adjoint uses; see
+                             rtx_tof_adjoint */
     RTX_INTERP_BSPLINE = 8u /* plan-wide (set at rtx_plan_create, fixed after):
                                interpolate c and its gradient with the
                                interpolating cubic B-spline of the node values
@@ -255,6 +263,12 @@ int rtx_march_free(rtx_plan plan, const double *c, int64_t n_rays, const double 
    its first adjoint call (as many as fit in 64 MiB, at most 8; with room for
    fewer than two they go to grad directly), and a final kernel adds the copies
    into grad and zeroes them again.
+   All pairs (pairs == NULL) after an RTX_FAN_START trace on the same plan,
+   with the same medium and path options (ds_px, integrator, max_steps) since:
+   a pair whose theta equals the angle that trace linked is marched as two
+   halves, the second starting from the trace's mid-path checkpoint (the same
+   samples as marching on, so the result is the same up to summation order);
+   any other pair is marched whole.
    Node updates pass through a bounded queue in on-chip memory; if one of its
    waits ever hits its bound, the gradient is incomplete and the next
    rtx_plan_stats call on the plan returns RTX_E_HIP. */

@@ -896,6 +896,32 @@ struct FanSeed {
 
 constexpr uint32_t kStraight = 1u << 16;  // internal: fixed pass at straight angles
 
+// Mid-path state of a ray traced by the fan-started linking pass: the adjoint
+// marches a linked ray as two halves, the second starting from this state
+// (position and direction hi/lo parts, the curvature the next step's cell
+// prediction uses, and the step index; m < 0: none).  Restarting there gives
+// the same samples as marching on.
+template <class R>
+struct RayCkpt {
+    R uh, ul, vh, vl, dxh, dxl, dyh, dyl, kx, ky;
+    int m;
+};
+
+// Per pair: the angle of its linked ray, the lane (0 or 1) whose checkpoint
+// belongs to that ray (-1: none), and the plan generation (medium and path
+// options) it was traced under.
+struct CkptHead {
+    double theta;
+    unsigned gen;
+    int lane;
+};
+
+// Step index of a pair's checkpoint: half the steps of its chord.
+__device__ __forceinline__ int ckpt_step(const Geo &g, double dphi)
+{
+    return (int)(g.R * fabs(sin(0.5 * dphi)) / g.ds);
+}
+
 struct TraceArgs {
     const int32_t *pairs;
     int64_t n_pairs;
@@ -910,6 +936,9 @@ struct TraceArgs {
     const FanSeed *seed;        // fan start: per-pair seeds
     const double *f_g, *f_T, *f_L;  // fan start: the pair's own straight ray
     const int8_t *f_st;
+    void *ckpt;                 // fan start: RayCkpt<R> [n_pairs][2] (or NULL)
+    CkptHead *ckpt_head;        // [n_pairs]
+    unsigned gen;               // plan generation written to the heads
 };
 
 __device__ __forceinline__ bool pair_of(const TraceArgs &A, const Geo &g, int64_t p, int &e, int &r)
@@ -1009,6 +1038,17 @@ struct AdjArgs {
     // CUs queue behind each other; with one copy per XCD the queues are eight
     // times shorter (measured on the 256x256 workload: adjoint 1.43 -> 1.25 ms)
     int n_copies;
+    // split (all pairs after a fan-started trace of this plan): every work
+    // item of the tile walk becomes two, the halves of its ray, the second
+    // starting from the linking pass's checkpoint when that checkpoint is the
+    // ray's (head: same angle, plan generation gen); otherwise the first half
+    // item marches the whole ray and the second does nothing.  The kernel time
+    // is the longest lane's, so halves shorten it (a lane takes two halves of
+    // different rays).
+    int split;
+    const void *ckpt;            // RayCkpt<R> [n_pairs][2]
+    const CkptHead *ckpt_head;   // [n_pairs]
+    unsigned gen;
 };
 
 // Work item of an all-pairs tile walk -> (e, r) and the canonical pair index.
@@ -1270,22 +1310,32 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     int e = 0, r = 0;
     double mine = 0;
     bool active = false, waiting = false;
+    RayCkpt<R> *ck = nullptr;  // this lane's checkpoint slot for the current pair
+    int m_ck = -1;             // its step index
+    // the pair's checkpoint head: the linked ray's angle and lane, or none
+    auto put_head = [&](double th, int lane_of) {
+        if (A.ckpt_head && j == 0) A.ckpt_head[p] = CkptHead{th, A.gen, lane_of};
+    };
 
     auto round_start = [&](double th, bool use_q, double th_q) {
         const double ref = L.nvalid > 0 ? L.thb : L.th0;
         mine = j == 0 ? th : (use_q && th_q != th ? th_q : th == ref ? th + 1e-4 : th - 0.1 * (th - ref));
         start_ray<R, COMP>(ray, g, em, mine);
+        if (ck) ck->m = -1;  // until this ray reaches the checkpoint step
         if (!BSP) slots_prime(M, C, ray, ds, INTEG);
     };
     auto next_pair = [&]() {
         while (p < A.n_pairs) {
             if (!pair_of(A, g, p, e, r)) {
                 if (j == 0) write_pair(A, p, A.theta[p], NAN, NAN, NAN, 0, RTX_RAY_BAD_INPUT);
+                put_head(NAN, -1);
                 p += stride;
                 continue;
             }
             em = emitter_of(g, e);
             dr = mod2pi(elem_angle(g, r) - em.pe);
+            ck = A.ckpt ? (RayCkpt<R> *)A.ckpt + 2 * p + j : nullptr;
+            m_ck = ckpt_step(g, dr);
             const double th0 = (dr - kPi) / 2.0;
             link_reset(L, th0);
             t4.n = t4.next = 0;
@@ -1329,6 +1379,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
                 nxt.Th = ray.Th;
                 nxt.Tl = ray.Tl;
                 nxt.m = ray.m + 1;
+                if (nxt.m == m_ck && ck)
+                    *ck = RayCkpt<R>{nxt.uh, nxt.ul, nxt.vh, nxt.vl, nxt.dxh, nxt.dxl, nxt.dyh, nxt.dyl, nxt.kx, nxt.ky,
+                                     nxt.m};
                 ray = nxt;
             } else {
                 n_rays++;
@@ -1378,6 +1431,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
         bool done = true;
         if (sa[0] == RTX_RAY_BAD_INPUT || sa[1] == RTX_RAY_BAD_INPUT) {
             if (j == 0) write_pair(A, p, L.th0, NAN, NAN, NAN, L.n_marches, RTX_RAY_BAD_INPUT);
+            put_head(NAN, -1);
         } else {
             int lk = -1;
             double lmiss = INFINITY;
@@ -1397,7 +1451,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
             }
             if (lk >= 0) {
                 if (j == 0) write_pair(A, p, ca[lk], Ta[lk], La[lk], lmiss, L.n_marches, RTX_RAY_LINKED);
+                put_head(ca[lk], lk);
             } else if (L.n_marches >= 2 * A.max_marches) {  // max_marches rounds
+                put_head(NAN, -1);  // the best ray may be an earlier round's
                 if (j == 0) {
                     if (L.best_miss < INFINITY)
                         write_pair(A, p, L.best_th, L.best_T, L.best_L, L.best_miss, L.n_marches,
@@ -1741,10 +1797,11 @@ __device__ __forceinline__ AdjRay<R> adj_ray_of(const Geo &g)
 // to the cell accumulator, whose outputs are handed to `sink`; on the step that
 // leaves the ring, the shortened last step and the interception point instead.
 // Returns false once the ray has ended (left the ring, met a bad sample or used
-// max_steps), with the accumulator flushed.
+// max_steps) or reached step stop_m (a first half), with the accumulator flushed.
 template <class R, bool COMP, int INTEG, class Sink>
 __device__ __forceinline__ bool adj_step(const Medium<R> &m, const Geo &gg, const AdjArgs &a, const AdjRay<R> &kr,
-                                         Ray<R> &ray, Slot<R> (&C)[3], CellAcc<R> &acc, Emit<R> &E, Sink &sink)
+                                         Ray<R> &ray, Slot<R> (&C)[3], CellAcc<R> &acc, Emit<R> &E, Sink &sink,
+                                         int stop_m)
 {
     Ray<R> nxt;
     StepOut<R> so = ray_step<R, COMP, INTEG>(m, C, ray, nxt, kr.ds);
@@ -1759,7 +1816,12 @@ __device__ __forceinline__ bool adj_step(const Medium<R> &m, const Geo &gg, cons
         sink();
         nxt.m = ray.m + 1;
         ray = nxt;
-        return true;
+        if (ray.m < stop_m) return true;
+        // a first half ends before the sample the second half starts with
+        E.mask = 0;
+        acc_flush(m.nx, acc, E);
+        sink();
+        return false;
     }
     if (crossed) {
         Hit hit = intersect<R>(gg, ray, nxt);
@@ -1805,7 +1867,7 @@ __global__ void __launch_bounds__(kBlock + kFlushLanes) k_adjoint(Medium<R> M, G
     unsigned qh = 0, qt = 0;
     const int64_t stride = (int64_t)gridDim.x * nm;
     int64_t p = (int64_t)blockIdx.x * nm + lane;
-    int64_t n_items = BATCH ? B.off[B.n_inst] : A.n_items;
+    int64_t n_items = BATCH ? B.off[B.n_inst] : A.split ? 2 * A.n_items : A.n_items;
     int64_t q = p;
     int k = 0;
     Medium<R> m = M;
@@ -1820,6 +1882,7 @@ __global__ void __launch_bounds__(kBlock + kFlushLanes) k_adjoint(Medium<R> M, G
     acc.a[0] = acc.a[1] = acc.a[2] = acc.a[3] = (R)0;
     Emit<R> E;
     E.mask = 0;
+    int stop_m = INT_MAX;  // a first half's end
     bool active = false;
     auto push = [&]() { q_push(q_ring, q_head, q_tail, lane, nm, qh, qt, E, BATCH ? (unsigned)k << 24 : 0u, A.err); };
 
@@ -1835,11 +1898,40 @@ __global__ void __launch_bounds__(kBlock + kFlushLanes) k_adjoint(Medium<R> M, G
                 kr = adj_ray_of<R>(gg);
             }
             int e, r;
-            bool ok = BATCH ? pair_of(TraceArgs{a.pairs}, gg, q, e, r) : adj_item(a, gg, p, e, r, q);
+            // split: items 128 w + 64 h + t are half h of tile item 64 w + t, so
+            // a wave's lanes take the same half of 64 neighbouring rays
+            const int half = !BATCH && a.split ? (int)((p >> 6) & 1) : 0;
+            const int64_t it = !BATCH && a.split ? ((p >> 7) << 6) | (p & 63) : p;
+            bool ok = BATCH ? pair_of(TraceArgs{a.pairs}, gg, q, e, r) : adj_item(a, gg, it, e, r, q);
             ok = ok && (a.status[q] == RTX_RAY_LINKED || a.status[q] == RTX_RAY_NOT_CONVERGED);
             double rho = ok ? a.rho[q] : 0.0;
+            RayCkpt<R> ckv;
+            ckv.m = -1;
+            if (!BATCH && a.split && ok && rho != 0.0) {
+                const CkptHead hd = a.ckpt_head[q];
+                if (hd.lane >= 0 && hd.gen == a.gen && hd.theta == a.theta[q])
+                    ckv = ((const RayCkpt<R> *)a.ckpt)[2 * q + hd.lane];
+                if (ckv.m <= 0 && half == 1) ok = false;  // no checkpoint: the first half takes the whole ray
+            }
             if (ok && rho != 0.0) {
-                start_ray<R, COMP>(ray, gg, emitter_of(gg, e), a.theta[q]);
+                if (half == 0) {
+                    start_ray<R, COMP>(ray, gg, emitter_of(gg, e), a.theta[q]);
+                    stop_m = ckv.m > 0 ? ckv.m : INT_MAX;
+                } else {
+                    ray.uh = ckv.uh;
+                    ray.ul = ckv.ul;
+                    ray.vh = ckv.vh;
+                    ray.vl = ckv.vl;
+                    ray.dxh = ckv.dxh;
+                    ray.dxl = ckv.dxl;
+                    ray.dyh = ckv.dyh;
+                    ray.dyl = ckv.dyl;
+                    ray.kx = ckv.kx;
+                    ray.ky = ckv.ky;
+                    ray.Th = ray.Tl = (R)0;
+                    ray.m = ckv.m;
+                    stop_m = INT_MAX;
+                }
                 slots_prime(m, C, ray, kr.ds, INTEG);
                 kr.scale = (R)(rho * gg.h);
                 active = true;
@@ -1854,7 +1946,7 @@ __global__ void __launch_bounds__(kBlock + kFlushLanes) k_adjoint(Medium<R> M, G
 
     while (active) {
         n_steps++;
-        if (adj_step<R, COMP, INTEG>(m, gg, a, kr, ray, C, acc, E, push)) continue;
+        if (adj_step<R, COMP, INTEG>(m, gg, a, kr, ray, C, acc, E, push, stop_m)) continue;
         n_rays++;
         if (BATCH) mark_done(B, k);
         p += stride;
@@ -2735,6 +2827,12 @@ struct rtx_plan_s {
     int8_t *f_st = nullptr;
     void *f_seed = nullptr;
     void *adj_cp = nullptr;  // adjoint: zeroed gradient copies (allocated on first use)
+    // fan start: mid-path checkpoints of the linking rays (RayCkpt [max_pairs][2])
+    // and per-pair heads, for the adjoint's split; gen counts changes of the
+    // medium and of the path options (step, integrator, step limit)
+    void *ckpt = nullptr;
+    CkptHead *ckpt_head = nullptr;
+    unsigned gen = 1;
     // optional per-kernel timing with HIP events on the launch stream
     bool timing = false;
     std::vector<hipEvent_t> ev[RTX_NUM_SLOTS];
@@ -2835,6 +2933,7 @@ int pack(rtx_plan_s *P, const double *c, hipStream_t s)
     }
     int64_t cells = (int64_t)(P->grid.nx - 1) * (P->grid.ny - 1);
     int blocks = (int)((cells + kBlock - 1) / kBlock);
+    P->gen++;  // checkpoints of rays through the previous medium no longer apply
     if (int rc = time_mark(P, RTX_SLOT_PACK, 0, s)) return rc;
     if (P->bsp) {
         const int nx = P->grid.nx, ny = P->grid.ny;
@@ -2923,6 +3022,13 @@ int launch_fan(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
             hipMalloc(&P->f_seed, sizeof(FanSeed) * P->max_pairs) != hipSuccess)
             return fail(RTX_E_NOMEM, "fan-start workspace");
     }
+    if (!P->ckpt && !P->bsp) {  // (B-spline plans have no adjoint)
+        if (hipMalloc(&P->ckpt, sizeof(RayCkpt<R>) * 2 * P->max_pairs) != hipSuccess ||
+            hipMalloc((void **)&P->ckpt_head, sizeof(CkptHead) * P->max_pairs) != hipSuccess)
+            return fail(RTX_E_NOMEM, "fan-start checkpoints");
+        // generation 0 is never current: no head applies before the pass writes it
+        HIP_TRY(hipMemset(P->ckpt_head, 0, sizeof(CkptHead) * P->max_pairs));
+    }
     // the fan rays seed the linking only: four tracing steps per fan step, at
     // most a pixel (never below the tracing step), the step limit scaled alike
     const double ds_fan = std::max(P->opts.ds_px, std::min(4.0 * P->opts.ds_px, 1.0));
@@ -2950,6 +3056,9 @@ int launch_fan(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
     A3.f_T = P->f_T;
     A3.f_L = P->f_L;
     A3.f_st = P->f_st;
+    A3.ckpt = P->ckpt;
+    A3.ckpt_head = P->ckpt_head;
+    A3.gen = P->gen;
     (void)n;
     Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
     auto kern = P->bsp ? (P->opts.integ == RTX_RK4 ? k_link2<R, COMP, 4, true> : k_link2<R, COMP, 2, true>)
@@ -3338,6 +3447,8 @@ int rtx_plan_destroy(rtx_plan P)
     if (P->rho) (void)hipFree(P->rho);
     if (P->omega) (void)hipFree(P->omega);
     if (P->adj_cp) (void)hipFree(P->adj_cp);
+    if (P->ckpt) (void)hipFree(P->ckpt);
+    if (P->ckpt_head) (void)hipFree(P->ckpt_head);
     delete P;
     return RTX_OK;
 }
@@ -3351,6 +3462,8 @@ int rtx_plan_set_opts(rtx_plan P, const rtx_opts *opts)
         return fail(RTX_E_ARG, "the interpolation (RTX_INTERP_BSPLINE) of a plan cannot change");
     int rc = check_opts(&P->grid, &P->ring, opts);
     if (rc) return rc;
+    if (opts->ds_px != P->opts.ds_px || opts->integ != P->opts.integ || opts->max_steps != P->opts.max_steps)
+        P->gen++;  // the rays' paths change
     P->opts = *opts;
     return RTX_OK;
 }
@@ -3541,11 +3654,18 @@ int rtx_tof_adjoint(rtx_plan P, const double *c, const int32_t *pairs, int64_t n
     A.err = P->err;
     A.tile = 0;
     A.n_items = n_pairs;
+    A.split = 0;
+    A.ckpt = P->ckpt;
+    A.ckpt_head = P->ckpt_head;
+    A.gen = P->gen;
     if (!pairs) {  // all ordered pairs: walk 16 x 16 element-cluster tiles
         const int n = P->ring.n_elem;
         A.tile = std::min(16, n);
         const int64_t nc = (n + A.tile - 1) / A.tile;
         A.n_items = nc * nc * A.tile * A.tile;
+        // halves from the fan start's checkpoints (the walk's items come in
+        // whole waves: nc^2 t^2 is a multiple of 64 when t = 16)
+        A.split = P->ckpt != nullptr && A.tile == 16;
     }
     if (P->opts.prec == RTX_F32C) return launch_adjoint<float, true>(P, A, (float *)grad, s);
     return launch_adjoint<double, false>(P, A, (double *)grad, s);

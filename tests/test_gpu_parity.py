@@ -193,6 +193,49 @@ def test_adjoint_accumulates_across_calls(rtx, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_adjoint_halves_from_fan_checkpoints(rtx, prec):
+    """After a fan-started trace the all-pairs adjoint marches each linked ray
+    as two halves, the second from the linking pass's mid-path checkpoint:
+    twice as many segments as rays, the same total steps, the oracle's adjoint
+    at the traced angles, and the whole-ray adjoint of a plan without
+    checkpoints; re-setting the medium (a new generation) and changing one
+    angle make the checkpoints stop applying (whole rays again)."""
+    n, h = 96, 0.5e-3
+    c = _gauss(n, h, seed=10)
+    ring = (32, 0.45 * n * h * 0.9, 0.0)
+    pairs = synth.all_pairs(32)
+    rho = synth.real_residual(len(pairs), 2005)
+    tol = 1e-11 if prec == "f64" else 1e-5
+    plan = rtx.Plan(n, n, h, *ring, prec=prec)
+    out = plan.trace(_dev(c), fan=True)
+    th, st = out["theta"], out["status"]
+    used = int(((_np(st) == oracle.LINKED) | (_np(st) == oracle.NOT_CONVERGED)).sum())
+    assert used == len(pairs)
+    g_split = _np(plan.adjoint(th, st, _dev(rho))).astype(np.float64)
+    steps_split, segs = plan.region_stats(2)
+    assert segs == 2 * used
+    gref = oracle.adjoint(c, h, ring, pairs, _np(th), rho, status=_np(st))
+    assert np.linalg.norm(g_split - gref) / np.linalg.norm(gref) < tol
+    fresh = rtx.Plan(n, n, h, *ring, prec=prec)
+    g_whole = _np(fresh.adjoint(th, st, _dev(rho), c=_dev(c))).astype(np.float64)
+    steps_whole, rays = fresh.region_stats(2)
+    fresh.close()
+    assert rays == used and steps_whole == steps_split
+    assert np.linalg.norm(g_split - g_whole) / np.linalg.norm(g_whole) < (1e-14 if prec == "f64" else 1e-6)
+    # the same plan after the medium is packed again: whole rays
+    g_reset = _np(plan.adjoint(th, st, _dev(rho), c=_dev(c))).astype(np.float64)
+    assert plan.region_stats(2)[1] == used
+    assert np.linalg.norm(g_reset - g_whole) / np.linalg.norm(g_whole) < (1e-14 if prec == "f64" else 1e-6)
+    # a fresh fan trace, then one pair's angle changed: that pair alone is whole
+    out = plan.trace(None, fan=True, out=out)
+    th2 = out["theta"].clone()
+    th2[5] += 1e-9
+    plan.adjoint(th2, st, _dev(rho))
+    assert plan.region_stats(2)[1] == 2 * used - 1
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
 def test_rayborn_adjoint_matches_oracle(rtx, prec):
     n, h = 96, 0.5e-3
     c = _gauss(n, h, seed=12)
