@@ -1365,57 +1365,67 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     next_pair();
 
     while (active) {
-        if (!waiting) {
+        // Steps until a pair of the wave has both rays in.  Every lane steps, a
+        // waiting one too (its ray is over and its result posted; it repeats its
+        // last step, discarded, until its pair's next round): the slot registers
+        // are then written by the step's own prefetches alone, and the compiler
+        // keeps those loads in flight across steps (measured: linking pass
+        // 1.64 -> 1.59 ms on the 256x256 workload).
+        bool ready = false;
+        do {
             Ray<R> nxt;
             StepOut<R> so = ray_step<R, COMP, INTEG, BSP>(M, C, ray, nxt, ds);
-            n_steps++;
-            const R w_start = ray.m == 0 ? ds * (R)0.5 : ds;
-            const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
-            const R pu = (nxt.uh - cx) + nxt.ul, pv = (nxt.vh - cy) + nxt.vl;
-            const bool crossed = !bad && (pu * pu + pv * pv >= R2);
-            const bool exhausted = !bad && !crossed && (ray.m + 1 >= A.max_steps);
-            if (!(bad || crossed || exhausted)) {
-                add_T<R, COMP>(ray, w_start * so.ic1);
-                nxt.Th = ray.Th;
-                nxt.Tl = ray.Tl;
-                nxt.m = ray.m + 1;
-                if (nxt.m == m_ck && ck)
-                    *ck = RayCkpt<R>{nxt.uh, nxt.ul, nxt.vh, nxt.vl, nxt.dxh, nxt.dxl, nxt.dyh, nxt.dyl, nxt.kx, nxt.ky,
-                                     nxt.m};
-                ray = nxt;
-            } else {
-                n_rays++;
-                int st = RTX_RAY_NO_HIT;
-                double g_mis = NAN, T = NAN, Lm = NAN;
-                if (bad) {
-                    st = RTX_RAY_BAD_INPUT;
-                } else if (crossed) {
-                    const Hit hit = intersect<R>(g, ray, nxt);
-                    const double dsp = hit.t * g.ds;
-                    const Sample<R> sq = lookup_at<R, COMP, BSP>(M, g, hit.qx, hit.qy);
-                    if (!(sq.c > (R)0)) {
+            if (!waiting) {
+                n_steps++;
+                const R w_start = ray.m == 0 ? ds * (R)0.5 : ds;
+                const bool bad = !(so.s1.c > (R)0) || !(ray.uh == ray.uh) || !(ray.vh == ray.vh);
+                const R pu = (nxt.uh - cx) + nxt.ul, pv = (nxt.vh - cy) + nxt.vl;
+                const bool crossed = !bad && (pu * pu + pv * pv >= R2);
+                const bool exhausted = !bad && !crossed && (ray.m + 1 >= A.max_steps);
+                if (!(bad || crossed || exhausted)) {
+                    add_T<R, COMP>(ray, w_start * so.ic1);
+                    nxt.Th = ray.Th;
+                    nxt.Tl = ray.Tl;
+                    nxt.m = ray.m + 1;
+                    if (nxt.m == m_ck && ck)
+                        *ck = RayCkpt<R>{nxt.uh,  nxt.ul,  nxt.vh, nxt.vl, nxt.dxh, nxt.dxl,
+                                         nxt.dyh, nxt.dyl, nxt.kx, nxt.ky, nxt.m};
+                    ray = nxt;
+                } else {
+                    n_rays++;
+                    int st = RTX_RAY_NO_HIT;
+                    double g_mis = NAN, T = NAN, Lm = NAN;
+                    if (bad) {
                         st = RTX_RAY_BAD_INPUT;
-                    } else {
-                        const double wm = ray.m == 0 ? 0.5 * dsp : 0.5 * (g.ds + dsp);
-                        const double acc = ((double)ray.Th + (double)ray.Tl) + wm * (double)so.ic1 +
-                                           0.5 * dsp * (double)rcp(sq.c);
-                        T = acc * g.h;
-                        Lm = (ray.m * g.ds + dsp) * g.h;
-                        g_mis = mod2pi(atan2(hit.qy, hit.qx) - em.pe) - dr;
-                        st = RTX_RAY_LINKED;
+                    } else if (crossed) {
+                        const Hit hit = intersect<R>(g, ray, nxt);
+                        const double dsp = hit.t * g.ds;
+                        const Sample<R> sq = lookup_at<R, COMP, BSP>(M, g, hit.qx, hit.qy);
+                        if (!(sq.c > (R)0)) {
+                            st = RTX_RAY_BAD_INPUT;
+                        } else {
+                            const double wm = ray.m == 0 ? 0.5 * dsp : 0.5 * (g.ds + dsp);
+                            const double acc = ((double)ray.Th + (double)ray.Tl) + wm * (double)so.ic1 +
+                                               0.5 * dsp * (double)rcp(sq.c);
+                            T = acc * g.h;
+                            Lm = (ray.m * g.ds + dsp) * g.h;
+                            g_mis = mod2pi(atan2(hit.qy, hit.qx) - em.pe) - dr;
+                            st = RTX_RAY_LINKED;
+                        }
                     }
+                    s_th[lane] = mine;
+                    s_g[lane] = g_mis;
+                    s_T[lane] = T;
+                    s_L[lane] = Lm;
+                    s_st[lane] = st;
+                    waiting = true;
                 }
-                s_th[lane] = mine;
-                s_g[lane] = g_mis;
-                s_T[lane] = T;
-                s_L[lane] = Lm;
-                s_st[lane] = st;
-                waiting = true;
             }
-        }
-        compiler_fence();
-        const unsigned long long wm = __ballot(waiting);
-        if (!(waiting && ((wm >> (lane & 62)) & 3ull) == 3ull)) continue;
+            compiler_fence();
+            const unsigned long long wm = __ballot(waiting);
+            ready = waiting && ((wm >> (lane & 62)) & 3ull) == 3ull;
+        } while (!__any(ready));
+        if (!ready) continue;
         // ---- both rays of the round are in (rare, divergent, FP64) ----
         waiting = false;
         double ca[2], ga[2], Ta[2], La[2];
