@@ -896,11 +896,10 @@ struct FanSeed {
 
 constexpr uint32_t kStraight = 1u << 16;  // internal: fixed pass at straight angles
 
-// Mid-path state of a ray traced by the fan-started linking pass: the adjoint
-// marches a linked ray as two halves, the second starting from this state
-// (position and direction hi/lo parts, the curvature the next step's cell
-// prediction uses, and the step index; m < 0: none).  Restarting there gives
-// the same samples as marching on.
+// State of a ray traced by the fan-started linking pass at the start of one of
+// its later segments (position and direction hi/lo parts, the curvature the
+// next step's cell prediction uses, and the step index; m < 0: none): the
+// adjoint restarts there, which gives the same samples as marching on.
 template <class R>
 struct RayCkpt {
     R uh, ul, vh, vl, dxh, dxl, dyh, dyl, kx, ky;
@@ -916,10 +915,14 @@ struct CkptHead {
     int lane;
 };
 
-// Step index of a pair's checkpoint: half the steps of its chord.
-__device__ __forceinline__ int ckpt_step(const Geo &g, double dphi)
+// The adjoint marches a linked ray in kSegs segments; the linking pass stores
+// the ray's state at the kSegs - 1 segment starts after the first, every
+// ckpt_stride steps (the chord's steps / kSegs; 0: a chord too short to split).
+constexpr int kSegs = 2;
+
+__device__ __forceinline__ int ckpt_stride(const Geo &g, double dphi)
 {
-    return (int)(g.R * fabs(sin(0.5 * dphi)) / g.ds);
+    return (int)(2.0 * g.R * fabs(sin(0.5 * dphi)) / (g.ds * kSegs));
 }
 
 struct TraceArgs {
@@ -936,7 +939,7 @@ struct TraceArgs {
     const FanSeed *seed;        // fan start: per-pair seeds
     const double *f_g, *f_T, *f_L;  // fan start: the pair's own straight ray
     const int8_t *f_st;
-    void *ckpt;                 // fan start: RayCkpt<R> [n_pairs][2] (or NULL)
+    void *ckpt;                 // fan start: RayCkpt<R> [n_pairs][2][kSegs - 1] (or NULL)
     CkptHead *ckpt_head;        // [n_pairs]
     unsigned gen;               // plan generation written to the heads
 };
@@ -1039,14 +1042,14 @@ struct AdjArgs {
     // times shorter (measured on the 256x256 workload: adjoint 1.43 -> 1.25 ms)
     int n_copies;
     // split (all pairs after a fan-started trace of this plan): every work
-    // item of the tile walk becomes two, the halves of its ray, the second
-    // starting from the linking pass's checkpoint when that checkpoint is the
-    // ray's (head: same angle, plan generation gen); otherwise the first half
-    // item marches the whole ray and the second does nothing.  The kernel time
-    // is the longest lane's, so halves shorten it (a lane takes two halves of
-    // different rays).
+    // item of the tile walk becomes kSegs, the segments of its ray, the later
+    // ones starting from the linking pass's checkpoints when those are the
+    // ray's (head: same angle, plan generation gen); otherwise the first
+    // segment's item marches the whole ray and the others do nothing.  The
+    // kernel time is the longest lane's, so segments shorten it (a lane takes
+    // the same segment of kSegs different rays).
     int split;
-    const void *ckpt;            // RayCkpt<R> [n_pairs][2]
+    const void *ckpt;            // RayCkpt<R> [n_pairs][2][kSegs - 1]
     const CkptHead *ckpt_head;   // [n_pairs]
     unsigned gen;
 };
@@ -1310,8 +1313,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     int e = 0, r = 0;
     double mine = 0;
     bool active = false, waiting = false;
-    RayCkpt<R> *ck = nullptr;  // this lane's checkpoint slot for the current pair
-    int m_ck = -1;             // its step index
+    RayCkpt<R> *ck = nullptr;  // this lane's checkpoint slots for the current pair
+    int stride_ck = 0;         // steps between them
+    int k_ck = 0, m_ck = -1;   // the next slot to write and its step index
     // the pair's checkpoint head: the linked ray's angle and lane, or none
     auto put_head = [&](double th, int lane_of) {
         if (A.ckpt_head && j == 0) A.ckpt_head[p] = CkptHead{th, A.gen, lane_of};
@@ -1321,7 +1325,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
         const double ref = L.nvalid > 0 ? L.thb : L.th0;
         mine = j == 0 ? th : (use_q && th_q != th ? th_q : th == ref ? th + 1e-4 : th - 0.1 * (th - ref));
         start_ray<R, COMP>(ray, g, em, mine);
-        if (ck) ck->m = -1;  // until this ray reaches the checkpoint step
+        if (ck)  // until this ray reaches them
+            for (int k = 0; k < kSegs - 1; k++) ck[k].m = -1;
+        k_ck = 0;
+        m_ck = stride_ck > 0 ? stride_ck : -1;
         if (!BSP) slots_prime(M, C, ray, ds, INTEG);
     };
     auto next_pair = [&]() {
@@ -1334,8 +1341,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
             }
             em = emitter_of(g, e);
             dr = mod2pi(elem_angle(g, r) - em.pe);
-            ck = A.ckpt ? (RayCkpt<R> *)A.ckpt + 2 * p + j : nullptr;
-            m_ck = ckpt_step(g, dr);
+            ck = A.ckpt ? (RayCkpt<R> *)A.ckpt + (2 * p + j) * (kSegs - 1) : nullptr;
+            stride_ck = ckpt_stride(g, dr);
             const double th0 = (dr - kPi) / 2.0;
             link_reset(L, th0);
             t4.n = t4.next = 0;
@@ -1387,9 +1394,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
                     nxt.Th = ray.Th;
                     nxt.Tl = ray.Tl;
                     nxt.m = ray.m + 1;
-                    if (nxt.m == m_ck && ck)
-                        *ck = RayCkpt<R>{nxt.uh,  nxt.ul,  nxt.vh, nxt.vl, nxt.dxh, nxt.dxl,
-                                         nxt.dyh, nxt.dyl, nxt.kx, nxt.ky, nxt.m};
+                    if (nxt.m == m_ck && ck) {
+                        ck[k_ck] = RayCkpt<R>{nxt.uh,  nxt.ul,  nxt.vh, nxt.vl, nxt.dxh, nxt.dxl,
+                                              nxt.dyh, nxt.dyl, nxt.kx, nxt.ky, nxt.m};
+                        k_ck++;
+                        m_ck = k_ck < kSegs - 1 ? m_ck + stride_ck : -1;
+                    }
                     ray = nxt;
                 } else {
                     n_rays++;
@@ -1855,10 +1865,12 @@ __device__ __forceinline__ bool adj_step(const Medium<R> &m, const Geo &gg, cons
 
 // Marching lanes are threads 0 .. nm-1 (nm = blockDim.x - 64); the last wave
 // drains their node updates into the grid.
-template <class R, bool COMP, int INTEG, bool BATCH>
+template <class R, bool COMP, int INTEG, bool BATCH, bool SPLIT = false>
 __global__ void __launch_bounds__(kBlock + kFlushLanes) k_adjoint(Medium<R> M, Geo g, AdjArgs A, R *grad,
                                                                    BatchArgs B)
 {
+    // SPLIT (A.split, all pairs only): the segments of the rays as work items
+    constexpr bool kSplit = SPLIT && !BATCH;
     // block b adds into copy b mod n_copies of the gradient (AdjArgs::n_copies)
     if (!BATCH) grad += (size_t)(blockIdx.x % A.n_copies) * M.nx * M.ny;
     __shared__ QEntry<R> q_ring[QRing<R>::kLen * kBlock];
@@ -1877,7 +1889,7 @@ __global__ void __launch_bounds__(kBlock + kFlushLanes) k_adjoint(Medium<R> M, G
     unsigned qh = 0, qt = 0;
     const int64_t stride = (int64_t)gridDim.x * nm;
     int64_t p = (int64_t)blockIdx.x * nm + lane;
-    int64_t n_items = BATCH ? B.off[B.n_inst] : A.split ? 2 * A.n_items : A.n_items;
+    int64_t n_items = BATCH ? B.off[B.n_inst] : kSplit ? kSegs * A.n_items : A.n_items;
     int64_t q = p;
     int k = 0;
     Medium<R> m = M;
@@ -1892,7 +1904,7 @@ __global__ void __launch_bounds__(kBlock + kFlushLanes) k_adjoint(Medium<R> M, G
     acc.a[0] = acc.a[1] = acc.a[2] = acc.a[3] = (R)0;
     Emit<R> E;
     E.mask = 0;
-    int stop_m = INT_MAX;  // a first half's end
+    int stop_m = INT_MAX;  // a segment's end
     bool active = false;
     auto push = [&]() { q_push(q_ring, q_head, q_tail, lane, nm, qh, qt, E, BATCH ? (unsigned)k << 24 : 0u, A.err); };
 
@@ -1908,25 +1920,34 @@ __global__ void __launch_bounds__(kBlock + kFlushLanes) k_adjoint(Medium<R> M, G
                 kr = adj_ray_of<R>(gg);
             }
             int e, r;
-            // split: items 128 w + 64 h + t are half h of tile item 64 w + t, so
-            // a wave's lanes take the same half of 64 neighbouring rays
-            const int half = !BATCH && a.split ? (int)((p >> 6) & 1) : 0;
-            const int64_t it = !BATCH && a.split ? ((p >> 7) << 6) | (p & 63) : p;
+            // split: items 64 (kSegs w + sg) + t are segment sg of tile item
+            // 64 w + t, so a wave's lanes take the same segment of 64
+            // neighbouring rays
+            const int sg = kSplit ? (int)((p >> 6) % kSegs) : 0;
+            const int64_t it = kSplit ? ((p >> 6) / kSegs << 6) | (p & 63) : p;
             bool ok = BATCH ? pair_of(TraceArgs{a.pairs}, gg, q, e, r) : adj_item(a, gg, it, e, r, q);
             ok = ok && (a.status[q] == RTX_RAY_LINKED || a.status[q] == RTX_RAY_NOT_CONVERGED);
             double rho = ok ? a.rho[q] : 0.0;
-            RayCkpt<R> ckv;
+            RayCkpt<R> ckv;  // the segment's start (sg > 0)
             ckv.m = -1;
-            if (!BATCH && a.split && ok && rho != 0.0) {
+            int seg_end = INT_MAX;
+            if (kSplit && ok && rho != 0.0) {
                 const CkptHead hd = a.ckpt_head[q];
-                if (hd.lane >= 0 && hd.gen == a.gen && hd.theta == a.theta[q])
-                    ckv = ((const RayCkpt<R> *)a.ckpt)[2 * q + hd.lane];
-                if (ckv.m <= 0 && half == 1) ok = false;  // no checkpoint: the first half takes the whole ray
+                const RayCkpt<R> *cks = (const RayCkpt<R> *)a.ckpt + (2 * q + max(hd.lane, 0)) * (kSegs - 1);
+                // the last checkpoint exists only if the ray wrote all of them
+                const bool have = hd.lane >= 0 && hd.gen == a.gen && hd.theta == a.theta[q] &&
+                                  cks[kSegs - 2].m > 0;
+                if (have) {
+                    if (sg > 0) ckv = cks[sg - 1];
+                    if (sg < kSegs - 1) seg_end = cks[sg].m;
+                } else if (sg > 0) {
+                    ok = false;  // no checkpoints: the first segment takes the whole ray
+                }
             }
             if (ok && rho != 0.0) {
-                if (half == 0) {
+                stop_m = seg_end;
+                if (sg == 0) {
                     start_ray<R, COMP>(ray, gg, emitter_of(gg, e), a.theta[q]);
-                    stop_m = ckv.m > 0 ? ckv.m : INT_MAX;
                 } else {
                     ray.uh = ckv.uh;
                     ray.ul = ckv.ul;
@@ -1940,7 +1961,6 @@ __global__ void __launch_bounds__(kBlock + kFlushLanes) k_adjoint(Medium<R> M, G
                     ray.ky = ckv.ky;
                     ray.Th = ray.Tl = (R)0;
                     ray.m = ckv.m;
-                    stop_m = INT_MAX;
                 }
                 slots_prime(m, C, ray, kr.ds, INTEG);
                 kr.scale = (R)(rho * gg.h);
@@ -3033,7 +3053,7 @@ int launch_fan(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
             return fail(RTX_E_NOMEM, "fan-start workspace");
     }
     if (!P->ckpt && !P->bsp) {  // (B-spline plans have no adjoint)
-        if (hipMalloc(&P->ckpt, sizeof(RayCkpt<R>) * 2 * P->max_pairs) != hipSuccess ||
+        if (hipMalloc(&P->ckpt, sizeof(RayCkpt<R>) * 2 * (kSegs - 1) * P->max_pairs) != hipSuccess ||
             hipMalloc((void **)&P->ckpt_head, sizeof(CkptHead) * P->max_pairs) != hipSuccess)
             return fail(RTX_E_NOMEM, "fan-start checkpoints");
         // generation 0 is never current: no head applies before the pass writes it
@@ -3103,7 +3123,9 @@ int launch_adjoint(rtx_plan_s *P, const AdjArgs &A, R *grad, hipStream_t s)
         HIP_TRY(hipMemset(P->adj_cp, 0, bytes));
     }
     a.n_copies = n_copies;
-    auto kern = P->opts.integ == RTX_RK4 ? k_adjoint<R, COMP, 4, false> : k_adjoint<R, COMP, 2, false>;
+    auto kern = a.split ? (P->opts.integ == RTX_RK4 ? k_adjoint<R, COMP, 4, false, true>
+                                                    : k_adjoint<R, COMP, 2, false, true>)
+                        : (P->opts.integ == RTX_RK4 ? k_adjoint<R, COMP, 4, false> : k_adjoint<R, COMP, 2, false>);
     int blocks = adjoint_blocks_for(P->n_cu, P->block, kern, A.n_items);
     P->stat_blocks[2] = blocks;
     BatchArgs B{};
@@ -3673,7 +3695,7 @@ int rtx_tof_adjoint(rtx_plan P, const double *c, const int32_t *pairs, int64_t n
         A.tile = std::min(16, n);
         const int64_t nc = (n + A.tile - 1) / A.tile;
         A.n_items = nc * nc * A.tile * A.tile;
-        // halves from the fan start's checkpoints (the walk's items come in
+        // segments from the fan start's checkpoints (the walk's items come in
         // whole waves: nc^2 t^2 is a multiple of 64 when t = 16)
         A.split = P->ckpt != nullptr && A.tile == 16;
     }

@@ -127,3 +127,43 @@ def test_c4_full_size(rtx, tmp_path):
     assert bool(torch.isfinite(g1).all())
     assert float((g2 - 2 * g1).norm() / g1.norm()) < 1e-5
     plan.close()
+
+
+def _oracle_adjoint_threads(c, h, ring, pairs, theta, rho, status, weight="length"):
+    """The oracle's adjoint over all pairs, summed from 64 chunks on a thread
+    pool (the oracle releases the GIL while it runs)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    chunks = np.array_split(np.arange(len(pairs)), 64)
+
+    def part(ix):
+        return oracle.adjoint(c, h, ring, pairs[ix], theta[ix], rho[ix], weight=weight, status=status[ix])
+
+    with ThreadPoolExecutor(16) as ex:
+        return sum(ex.map(part, chunks))
+
+
+@pytest.mark.parametrize("prec", ["f32c", "f64"])
+def test_adjoint_full_size_several_items_per_lane(rtx, prec):
+    """384x384 smooth field, 512-element ring (261,632 pairs, four tile items
+    per adjoint lane): the all-pairs adjoint against the oracle's over every
+    pair, after a straight-start trace (whole rays) and after a fan-started
+    trace (rays in segments from the linking pass's checkpoints: two per
+    ray)."""
+    cfg, c = synth.make_config("c3_smooth_384")
+    ring = (cfg["n_elem"], cfg["radius"], cfg["phi0"])
+    pairs = synth.all_pairs(cfg["n_elem"])
+    rho = synth.real_residual(len(pairs), 5, 1e-4)
+    tol = 1e-5 if prec == "f32c" else 1e-11
+    plan = rtx.Plan(cfg["nx"], cfg["ny"], cfg["h"], *ring, prec=prec)
+    for fan, per_ray in ((False, 1), (True, 2)):
+        out = plan.trace(_dev(c), fan=fan)
+        st = out["status"].cpu().numpy()
+        g = plan.adjoint(out["theta"], out["status"], _dev(rho)).double().cpu().numpy()
+        used = int(((st == oracle.LINKED) | (st == oracle.NOT_CONVERGED)).sum())
+        assert plan.region_stats(2)[1] == per_ray * used
+        gref = _oracle_adjoint_threads(c, cfg["h"], ring, pairs, out["theta"].cpu().numpy(), rho, st)
+        err = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+        print(f"\n{prec} fan={fan}: adjoint rel L2 {err:.2e} over {used} rays", flush=True)
+        assert err < tol
+    plan.close()

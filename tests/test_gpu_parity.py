@@ -193,13 +193,13 @@ def test_adjoint_accumulates_across_calls(rtx, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32c"])
-def test_adjoint_halves_from_fan_checkpoints(rtx, prec):
+def test_adjoint_segments_from_fan_checkpoints(rtx, prec):
     """After a fan-started trace the all-pairs adjoint marches each linked ray
-    as two halves, the second from the linking pass's mid-path checkpoint:
-    twice as many segments as rays, the same total steps, the oracle's adjoint
-    at the traced angles, and the whole-ray adjoint of a plan without
-    checkpoints; re-setting the medium (a new generation) and changing one
-    angle make the checkpoints stop applying (whole rays again)."""
+    in segments (two), the later ones from the linking pass's checkpoints: two
+    segments per ray, the same total steps, the oracle's adjoint at the traced
+    angles, and the whole-ray adjoint of a plan without checkpoints;
+    re-setting the medium (a new generation) and changing one angle make the
+    checkpoints stop applying (whole rays again)."""
     n, h = 96, 0.5e-3
     c = _gauss(n, h, seed=10)
     ring = (32, 0.45 * n * h * 0.9, 0.0)
