@@ -937,7 +937,7 @@ struct TraceArgs {
     unsigned long long *stats;  // [gridDim.x][2]: steps, rays
     double *gsig;               // fixed pass: signed misfit of each ray (or NULL)
     const FanSeed *seed;        // fan start: per-pair seeds
-    const double *f_g, *f_T, *f_L;  // fan start: the pair's own straight ray
+    const double *f_g;          // fan start: the signed misfit of the pair's own straight ray
     const int8_t *f_st;
     void *ckpt;                 // fan start: RayCkpt<R> [n_pairs][2][kSegs - 1] (or NULL)
     CkptHead *ckpt_head;        // [n_pairs]
@@ -2100,17 +2100,23 @@ __global__ void __launch_bounds__(kBlock) k_fan_seed(Geo g, const double *__rest
         sd.th_far = sd.g_far = sd.th_near = sd.g_near = sd.th_first = sd.th_q = 0.0;
         sd.cubic = found >= 0 && fan_inverse<2>(g, e, H, Dr, n, found, sd.th_first);
         sd.quintic = found >= 0 && fan_inverse<3>(g, e, H, Dr, n, found, sd.th_q);
+        // the samples that hit, packed in order (unrolled, so that the record
+        // stays in registers)
         sd.n_s = 0;
         for (int q = 0; q < 4; q++) sd.s_th[q] = sd.s_g[q] = 0.0;
-        if (found >= 0)
-            for (int a = found - 1; a <= found + 2; a++) {
-                if (a < 0 || a > n - 2) continue;
-                const double ga = H[a] - Dr;
-                if (!(ga == ga)) continue;
-                sd.s_th[sd.n_s] = fan_straight(g, e, a + 1);
-                sd.s_g[sd.n_s] = ga;
-                sd.n_s++;
-            }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int a = found - 1 + u;
+            const bool use = found >= 0 && a >= 0 && a <= n - 2 && H[a] - Dr == H[a] - Dr;
+            const double ga = use ? H[a] - Dr : 0.0, ta = use ? fan_straight(g, e, a + 1) : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (use && q == sd.n_s) {
+                    sd.s_th[q] = ta;
+                    sd.s_g[q] = ga;
+                }
+            sd.n_s += use;
+        }
         if (found >= 0) {
             double ga = H[found] - Dr, gb = H[found + 1] - Dr;
             int nr = fabs(ga) <= fabs(gb) ? found : found + 1;
@@ -2853,7 +2859,7 @@ struct rtx_plan_s {
     int n_cu = 0;
     int block = kBlock;  // threads (rays) per block of the persistent kernels
     // fan-start workspace (allocated on first use): own straight ray of each pair
-    double *f_g = nullptr, *f_T = nullptr, *f_L = nullptr;
+    double *f_g = nullptr;
     int8_t *f_st = nullptr;
     void *f_seed = nullptr;
     void *adj_cp = nullptr;  // adjoint: zeroed gradient copies (allocated on first use)
@@ -3046,8 +3052,6 @@ int launch_fan(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
     const int64_t n = A.n_pairs;
     if (!P->f_g) {
         if (hipMalloc((void **)&P->f_g, sizeof(double) * P->max_pairs) != hipSuccess ||
-            hipMalloc((void **)&P->f_T, sizeof(double) * P->max_pairs) != hipSuccess ||
-            hipMalloc((void **)&P->f_L, sizeof(double) * P->max_pairs) != hipSuccess ||
             hipMalloc((void **)&P->f_st, sizeof(int8_t) * P->max_pairs) != hipSuccess ||
             hipMalloc(&P->f_seed, sizeof(FanSeed) * P->max_pairs) != hipSuccess)
             return fail(RTX_E_NOMEM, "fan-start workspace");
@@ -3064,8 +3068,8 @@ int launch_fan(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
     const double ds_fan = std::max(P->opts.ds_px, std::min(4.0 * P->opts.ds_px, 1.0));
     TraceArgs A1 = A;
     A1.flags = RTX_FIXED_ANGLE | kStraight;
-    A1.tof = P->f_T;
-    A1.len = P->f_L;
+    A1.tof = nullptr;  // the seed rays' misfits and statuses only
+    A1.len = nullptr;
     A1.miss = nullptr;
     A1.n_marches = nullptr;
     A1.status = P->f_st;
@@ -3083,8 +3087,6 @@ int launch_fan(rtx_plan_s *P, const TraceArgs &A, hipStream_t s)
     A3.gsig = nullptr;
     A3.seed = (const FanSeed *)P->f_seed;
     A3.f_g = P->f_g;
-    A3.f_T = P->f_T;
-    A3.f_L = P->f_L;
     A3.f_st = P->f_st;
     A3.ckpt = P->ckpt;
     A3.ckpt_head = P->ckpt_head;
@@ -3472,7 +3474,7 @@ int rtx_plan_destroy(rtx_plan P)
     if (P->bsp_q) (void)hipFree(P->bsp_q);
     if (P->sart) (void)hipFree(P->sart);
     if (P->sart_csc) (void)hipFree(P->sart_csc);
-    for (void *q : {(void *)P->f_g, (void *)P->f_T, (void *)P->f_L, (void *)P->f_st, P->f_seed})
+    for (void *q : {(void *)P->f_g, (void *)P->f_st, P->f_seed})
         if (q) (void)hipFree(q);
     for (int k = 0; k < RTX_NUM_SLOTS; k++)
         for (hipEvent_t e : P->ev[k]) (void)hipEventDestroy(e);
@@ -3547,7 +3549,7 @@ int rtx_trace_rays(rtx_plan P, const double *c, const int32_t *pairs, int64_t n_
     A.stats = P->stats;
     A.gsig = nullptr;
     A.seed = nullptr;
-    A.f_g = A.f_T = A.f_L = nullptr;
+    A.f_g = nullptr;
     A.f_st = nullptr;
     P->stat_blocks[1] = 0;
     const bool fan = (A.flags & RTX_FAN_START) != 0;
