@@ -189,14 +189,15 @@ int rtx_tof_forward(rtx_plan plan, const double *c, const int32_t *pairs, int64_
      b        [n_rows] float64 (device): data, e.g. travel-time residuals (s)
      x        [ny * nx] float64 (device, in/out): start and result, e.g. the
               slowness update (s/m); column index = iy * nx + ix
-   The call transposes W once (CSC, built on the device; the order of the
-   entries inside a column, and so the rounding of the column sums, varies
-   between runs) and then streams W by rows and by columns each iteration;
-   arithmetic is FP64.  w_rowptr must be non-decreasing (otherwise the result
-   is undefined; memory accesses stay in bounds).  Plan-owned scratch: about
-   (2 max_pairs + 2.5 nx ny) x 8 bytes on first use, and (4 + value size) x nnz
-   bytes for the transpose, grown when a larger W arrives (a call that grows
-   it frees and allocates).
+   The call transposes W once (CSC, built on the device by a stable radix
+   sort of the entries by column, so rows stay ascending inside a column and
+   the result is the same on every run) and then streams W by rows and by
+   columns each iteration; arithmetic is FP64.  w_rowptr must be
+   non-decreasing (otherwise the result is undefined; memory accesses stay in
+   bounds).  Plan-owned scratch: about (2 max_pairs + 2 nx ny) x 8 bytes on
+   first use, and about 2 (8 + entry size) x nnz bytes for the transpose and
+   the sort (entry size 8 for float, 16 for double), grown when a larger W
+   arrives (a call that grows it frees and allocates).
    Errors: n_rows < 0 or > max_pairs, nnz < 0, n_iter < 0, lambda outside
    (0, 2), missing buffers -> RTX_E_ARG (nothing enqueued); RTX_E_NOMEM.
    n_rows == 0 or n_iter == 0 leaves x unchanged. */

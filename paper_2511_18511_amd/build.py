@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", "rtx.hip"), os.path.join(HERE, "csrc", "rtx3d.hip")]
+SRC = [os.path.join(HERE, "csrc", n) for n in ("rtx.hip", "rtx3d.hip", "sart_sort.hip")]
 LIB = os.path.join(HERE, "librtx.so")
 
 HIPCC_FLAGS = [

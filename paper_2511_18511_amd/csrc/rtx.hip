@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "rtx.h"
+#include "sart_sort.h"
 
 namespace {
 
@@ -2655,124 +2656,119 @@ __global__ void __launch_bounds__(kBlock)
 // ------------------------------------------------------------------- SART --
 // SART on the system matrix W (Sec. 3.1's default solver of the linearised ToF
 // subproblem).  Every step streams W with one wave per row (CSR) or per column
-// (CSC), the line's entries read by consecutive lanes, and gathers from a small
-// L2-resident vector:
-//   once per call: row sums M_i and column counts (CSR pass), column offsets
-//   (one-block scan), the transpose (CSR pass placing each entry in its
-//   column; the order inside a column varies between runs), column sums V_j
-//   (CSC pass);
+// (CSC), the line's entries read by consecutive lanes, kSartU entries in flight
+// per lane, and gathers from a small L2-resident vector:
+//   once per call: row sums M_i and the sort input (CSR pass: every entry keyed
+//   by its column, carrying its row and weight), a stable radix sort of the
+//   entries by column (the transpose; rows stay ascending inside a column, so
+//   the result does not depend on the run), column offsets from the sorted
+//   keys, column sums V_j (CSC pass);
 //   per iteration: r_i = (b_i - W_i x) / M_i (CSR pass), then
 //   x_j += lambda / V_j sum_i W_ij r_i (CSC pass).
 // No float atomics; all sums in FP64.  Entries whose column lies outside
-// [0, n_nodes) are left out.
+// [0, n_nodes), and entries in no row, are sorted into the last column with
+// row -1 and left out.  (Measured on the 256x256 workload: 8 entries in flight
+// per lane, non-temporal loads, or persistent waves that load the next line
+// before the current one's gathers wait were no faster, or slower, than this
+// plain form.)
+constexpr int kSartU = 4;
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_fill(T *__restrict__ a, int64_t n, T v)
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+
+// one entry of the transpose in a single load
+__device__ __forceinline__ CscEnt<float> load_ent(const CscEnt<float> *p)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = v;
+    const u32x2_t v = *(const u32x2_t *)p;
+    return {(int32_t)v.x, __uint_as_float(v.y)};
+}
+__device__ __forceinline__ CscEnt<double> load_ent(const CscEnt<double> *p)
+{
+    const u32x4_t v = *(const u32x4_t *)p;
+    return {(int32_t)v.x, __hiloint2double((int)v.w, (int)v.z)};
 }
 
-// M_i and the entry count of every column.
+// M_i, and every entry's sort key (its column) and payload (row, weight).  Wave
+// n_rows takes the entries before the first row and after the last.
 template <class R>
 __global__ void __launch_bounds__(kBlock)
-    k_sart_count(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col, const R *__restrict__ val,
-                 int64_t n_rows, int64_t nnz, int64_t n_nodes, double *__restrict__ M, unsigned *__restrict__ cnt)
+    k_sart_rows(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col, const R *__restrict__ val,
+                int64_t n_rows, int64_t nnz, int64_t n_nodes, double *__restrict__ M, uint32_t *__restrict__ key,
+                CscEnt<R> *__restrict__ ent)
 {
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (i >= n_rows) return;
+    if (i > n_rows) return;
+    const uint32_t last = (uint32_t)(n_nodes - 1);
+    if (i == n_rows) {
+        const int64_t a = min(max(rowptr[0], (int64_t)0), nnz), z = max(min(rowptr[n_rows], nnz), a);
+        for (int64_t k = lane; k < a; k += 64) key[k] = last, ent[k] = {-1, (R)0};
+        for (int64_t k = z + lane; k < nnz; k += 64) key[k] = last, ent[k] = {-1, (R)0};
+        return;
+    }
     double m = 0.0;
     const int64_t k1 = min(rowptr[i + 1], nnz);
-    for (int64_t k0 = max(rowptr[i], (int64_t)0) + lane; k0 < k1; k0 += 4 * 64) {
-        int32_t j[4];
-        R w[4];
-        for (int u = 0; u < 4; u++) {  // four entries in flight per lane
+    for (int64_t k0 = max(rowptr[i], (int64_t)0) + lane; k0 < k1; k0 += kSartU * 64) {
+        int32_t j[kSartU];
+        R w[kSartU];
+#pragma unroll
+        for (int u = 0; u < kSartU; u++) {
             const int64_t k = k0 + 64 * u;
             j[u] = k < k1 ? col[k] : -1;
             w[u] = k < k1 ? val[k] : (R)0;
         }
-        for (int u = 0; u < 4; u++) {
-            if ((uint64_t)j[u] >= (uint64_t)n_nodes) continue;
-            m += (double)w[u];
-            atomicAdd(cnt + j[u], 1u);
+#pragma unroll
+        for (int u = 0; u < kSartU; u++) {
+            const int64_t k = k0 + 64 * u;
+            if (k >= k1) continue;
+            const bool ok = (uint64_t)j[u] < (uint64_t)n_nodes;
+            key[k] = ok ? (uint32_t)j[u] : last;
+            ent[k] = {ok ? (int32_t)i : -1, w[u]};
+            if (ok) m += (double)w[u];
         }
     }
     m = wave_sum(m);
     if (lane == 0) M[i] = m;
 }
 
-// Exclusive scan of the counts into colptr[0..n] (one block); clears cnt for
-// use as the fill cursor.
-__global__ void __launch_bounds__(1024) k_sart_scan(unsigned *__restrict__ cnt, int64_t n, int64_t *__restrict__ colptr)
-{
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (n + 1023) / 1024, lo = min((int64_t)t * per, n), hi = min(lo + per, n);
-    int64_t sum = 0;
-    for (int64_t j = lo; j < hi; j++) sum += cnt[j];
-    part[t] = sum;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scan of the parts
-        const int64_t v = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int64_t run = t ? part[t - 1] : 0;
-    for (int64_t j = lo; j < hi; j++) {
-        colptr[j] = run;
-        run += cnt[j];
-        cnt[j] = 0;
-    }
-    if (t == 1023) colptr[n] = part[1023];
-}
-
-template <class R>
+// colptr[j] = the first sorted position whose key is >= j, for j in [0, n]: a
+// binary search over the sorted keys (clamped to n - 1) per column.
 __global__ void __launch_bounds__(kBlock)
-    k_sart_place(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col, const R *__restrict__ val,
-                 int64_t n_rows, int64_t nnz, int64_t n_nodes, const int64_t *__restrict__ colptr,
-                 unsigned *__restrict__ cur, int32_t *__restrict__ crow, R *__restrict__ cval, int64_t cap)
+    k_sart_bounds(const uint32_t *__restrict__ key, int64_t nnz, int64_t n, int64_t *__restrict__ colptr)
 {
-    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (i >= n_rows) return;
-    const int64_t k1 = min(rowptr[i + 1], nnz);
-    for (int64_t k0 = max(rowptr[i], (int64_t)0) + lane; k0 < k1; k0 += 4 * 64) {
-        int32_t j[4];
-        R w[4];
-        int64_t pos[4];
-        for (int u = 0; u < 4; u++) {  // four entries in flight per lane
-            const int64_t k = k0 + 64 * u;
-            j[u] = k < k1 ? col[k] : -1;
-            w[u] = k < k1 ? val[k] : (R)0;
-        }
-        for (int u = 0; u < 4; u++)
-            pos[u] = (uint64_t)j[u] < (uint64_t)n_nodes ? colptr[j[u]] + atomicAdd(cur + j[u], 1u) : cap;
-        for (int u = 0; u < 4; u++) {
-            if (pos[u] >= cap) continue;  // an invalid column, or a row pointer that is not monotone
-            crow[pos[u]] = (int32_t)i;
-            cval[pos[u]] = w[u];
-        }
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > n) return;
+    int64_t lo = 0, hi = nnz;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (min((int64_t)key[mid], n - 1) < j)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
+    colptr[j] = lo;
 }
 
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_sart_colsum(const int64_t *__restrict__ colptr,
-                                                        const R *__restrict__ cval, int64_t n_nodes, int64_t cap,
-                                                        double *__restrict__ V)
+                                                        const CscEnt<R> *__restrict__ ent, int64_t n_nodes,
+                                                        int64_t n_rows, int64_t nnz, double *__restrict__ V)
 {
     const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (j >= n_nodes) return;
     double v = 0.0;
-    const int64_t k1 = min(colptr[j + 1], cap);
-    for (int64_t k = colptr[j] + lane; k < k1; k += 64) v += (double)cval[k];
+    const int64_t k1 = min(colptr[j + 1], nnz);
+    for (int64_t k = colptr[j] + lane; k < k1; k += 64) {
+        const CscEnt<R> e = load_ent(ent + k);
+        if ((uint64_t)e.row < (uint64_t)n_rows) v += (double)e.val;
+    }
     v = wave_sum(v);
     if (lane == 0) V[j] = v;
 }
@@ -2790,17 +2786,20 @@ __global__ void __launch_bounds__(kBlock)
     double proj = 0.0;
     const int64_t k1 = min(rowptr[i + 1], nnz);
     if (m != 0.0)
-        for (int64_t k0 = max(rowptr[i], (int64_t)0) + lane; k0 < k1; k0 += 4 * 64) {
-            int32_t j[4];
-            R w[4];
-            for (int u = 0; u < 4; u++) {  // four entries in flight per lane
+        for (int64_t k0 = max(rowptr[i], (int64_t)0) + lane; k0 < k1; k0 += kSartU * 64) {
+            int32_t j[kSartU];
+            R w[kSartU];
+#pragma unroll
+            for (int u = 0; u < kSartU; u++) {
                 const int64_t k = k0 + 64 * u;
                 j[u] = k < k1 ? col[k] : -1;
                 w[u] = k < k1 ? val[k] : (R)0;
             }
-            double xv[4];
-            for (int u = 0; u < 4; u++) xv[u] = (uint64_t)j[u] < (uint64_t)n_nodes ? x[j[u]] : 0.0;
-            for (int u = 0; u < 4; u++) proj = fma((double)w[u], xv[u], proj);
+            double xv[kSartU];
+#pragma unroll
+            for (int u = 0; u < kSartU; u++) xv[u] = (uint64_t)j[u] < (uint64_t)n_nodes ? x[j[u]] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kSartU; u++) proj = fma((double)w[u], xv[u], proj);
         }
     proj = wave_sum(proj);
     if (lane == 0) r[i] = m != 0.0 ? (b[i] - proj) / m : 0.0;
@@ -2808,8 +2807,8 @@ __global__ void __launch_bounds__(kBlock)
 
 template <class R>
 __global__ void __launch_bounds__(kBlock)
-    k_sart_back(const int64_t *__restrict__ colptr, const int32_t *__restrict__ crow, const R *__restrict__ cval,
-                int64_t n_nodes, int64_t cap, const double *__restrict__ r, const double *__restrict__ V,
+    k_sart_back(const int64_t *__restrict__ colptr, const CscEnt<R> *__restrict__ ent, int64_t n_nodes,
+                int64_t n_rows, int64_t nnz, const double *__restrict__ r, const double *__restrict__ V,
                 double lambda, double *__restrict__ x)
 {
     const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -2818,18 +2817,19 @@ __global__ void __launch_bounds__(kBlock)
     const double v = V[j];
     if (v == 0.0) return;
     double u = 0.0;
-    const int64_t k1 = min(colptr[j + 1], cap);
-    for (int64_t k0 = colptr[j] + lane; k0 < k1; k0 += 4 * 64) {
-        int32_t q[4];
-        R w[4];
-        for (int t = 0; t < 4; t++) {  // four entries in flight per lane
+    const int64_t k1 = min(colptr[j + 1], nnz);
+    for (int64_t k0 = colptr[j] + lane; k0 < k1; k0 += kSartU * 64) {
+        CscEnt<R> e[kSartU];
+#pragma unroll
+        for (int t = 0; t < kSartU; t++) {
             const int64_t k = k0 + 64 * t;
-            q[t] = k < k1 ? crow[k] : -1;
-            w[t] = k < k1 ? cval[k] : (R)0;
+            e[t] = k < k1 ? load_ent(ent + k) : CscEnt<R>{-1, (R)0};
         }
-        double rv[4];
-        for (int t = 0; t < 4; t++) rv[t] = q[t] >= 0 ? r[q[t]] : 0.0;
-        for (int t = 0; t < 4; t++) u = fma((double)w[t], rv[t], u);
+        double rv[kSartU];
+#pragma unroll
+        for (int t = 0; t < kSartU; t++) rv[t] = (uint64_t)e[t].row < (uint64_t)n_rows ? r[e[t].row] : 0.0;
+#pragma unroll
+        for (int t = 0; t < kSartU; t++) u = fma((double)e[t].val, rv[t], u);
     }
     u = wave_sum(u);
     if (lane == 0) x[j] += lambda * u / v;
@@ -2846,8 +2846,8 @@ struct rtx_plan_s {
     void *tab = nullptr;  // packed medium
     bool have_medium = false;
     void *sart = nullptr;      // SART scratch: M, r [max_pairs]; V [nx*ny]; colptr [nx*ny+1]; counts
-    void *sart_csc = nullptr;  // SART transpose of W: rows (int32) and values, for sart_cap entries
-    int64_t sart_cap = 0;
+    void *sart_csc = nullptr;  // SART transpose of W and the sort's buffers (sart_csc_bytes)
+    size_t sart_csc_bytes = 0;
     bool bsp = false;          // cubic B-spline interpolation (RTX_INTERP_BSPLINE)
     double *bsp_q = nullptr;   // [ny][nx] B-spline coefficients (FP64)
     unsigned long long *stats = nullptr;  // [3][kMaxBlocks][2]: trace, fan link pass, adjoint
@@ -3377,6 +3377,8 @@ int launch_march(rtx_plan_s *P, int64_t n_rays, const double *x0, const double *
     return RTX_OK;
 }
 
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 template <class R>
 int launch_sart(rtx_plan_s *P, int64_t n_rows, int64_t nnz, const int64_t *rowptr, const int32_t *col, const R *val,
                 const double *b, double *x, int n_iter, double lambda, hipStream_t s)
@@ -3384,37 +3386,44 @@ int launch_sart(rtx_plan_s *P, int64_t n_rows, int64_t nnz, const int64_t *rowpt
     const int64_t nodes = (int64_t)P->grid.nx * P->grid.ny;
     double *M = (double *)P->sart, *r = M + P->max_pairs, *V = r + P->max_pairs;
     int64_t *colptr = (int64_t *)(V + nodes);
-    unsigned *cnt = (unsigned *)(colptr + nodes + 1);
-    // the transpose holds at most nnz entries: every kernel reads entries k < nnz only
-    if (nnz > P->sart_cap) {
+    unsigned end_bit = 1;  // keys are columns, < nodes
+    while (end_bit < 32 && ((int64_t)1 << end_bit) < nodes) end_bit++;
+    // plan-owned: the transpose, the sort's input entries, keys in and out, and
+    // the sort's own scratch
+    size_t tmp_bytes = 0;
+    if (nnz > 0)
+        HIP_TRY(csc_sort<R>(nullptr, tmp_bytes, nullptr, nullptr, nullptr, nullptr, (size_t)nnz, end_bit, s));
+    const size_t b_ent = align256(sizeof(CscEnt<R>) * (size_t)nnz), b_key = align256(sizeof(uint32_t) * (size_t)nnz);
+    const size_t need = 2 * b_ent + 2 * b_key + align256(tmp_bytes);
+    if (need > P->sart_csc_bytes) {
         if (P->sart_csc) (void)hipFree(P->sart_csc);
         P->sart_csc = nullptr;
-        P->sart_cap = 0;
-        const int64_t cap = (nnz + 1) & ~(int64_t)1;  // even: keeps the value array 8-byte aligned
-        if (hipMalloc(&P->sart_csc, (sizeof(int32_t) + sizeof(R)) * (size_t)cap) != hipSuccess) {
+        P->sart_csc_bytes = 0;
+        if (hipMalloc(&P->sart_csc, need) != hipSuccess) {
             P->sart_csc = nullptr;
             return fail(RTX_E_NOMEM, "SART transpose allocation (%lld entries) failed", (long long)nnz);
         }
-        P->sart_cap = cap;
+        P->sart_csc_bytes = need;
     }
-    int32_t *crow = (int32_t *)P->sart_csc;
-    R *cval = (R *)(crow + P->sart_cap);
+    char *base = (char *)P->sart_csc;
+    CscEnt<R> *ent = (CscEnt<R> *)base, *ent_in = (CscEnt<R> *)(base + b_ent);
+    uint32_t *key_in = (uint32_t *)(base + 2 * b_ent), *key = (uint32_t *)(base + 2 * b_ent + b_key);
+    void *tmp = base + 2 * b_ent + 2 * b_key;
     const unsigned rb = (unsigned)((n_rows * 64 + kBlock - 1) / kBlock);
     const unsigned cb = (unsigned)((nodes * 64 + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_fill<unsigned>, dim3((unsigned)((nodes + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, cnt,
-                       nodes, 0u);
-    hipLaunchKernelGGL(k_sart_count<R>, dim3(rb), dim3(kBlock), 0, s, rowptr, col, val, n_rows, nnz, nodes, M, cnt);
-    hipLaunchKernelGGL(k_sart_scan, dim3(1), dim3(1024), 0, s, cnt, nodes, colptr);
-    hipLaunchKernelGGL(k_sart_place<R>, dim3(rb), dim3(kBlock), 0, s, rowptr, col, val, n_rows, nnz, nodes,
-                       (const int64_t *)colptr, cnt, crow, cval, P->sart_cap);
-    hipLaunchKernelGGL(k_sart_colsum<R>, dim3(cb), dim3(kBlock), 0, s, (const int64_t *)colptr, (const R *)cval,
-                       nodes, P->sart_cap, V);
+    hipLaunchKernelGGL(k_sart_rows<R>, dim3((unsigned)(((n_rows + 1) * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, rowptr, col, val, n_rows, nnz, nodes, M, key_in, ent_in);
+    if (nnz > 0) HIP_TRY(csc_sort<R>(tmp, tmp_bytes, key_in, key, ent_in, ent, (size_t)nnz, end_bit, s));
+    hipLaunchKernelGGL(k_sart_bounds, dim3((unsigned)((nodes + 1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       (const uint32_t *)key, nnz, nodes, colptr);
+    hipLaunchKernelGGL(k_sart_colsum<R>, dim3(cb), dim3(kBlock), 0, s, (const int64_t *)colptr,
+                       (const CscEnt<R> *)ent, nodes, n_rows, nnz, V);
     for (int it = 0; it < n_iter; it++) {
         hipLaunchKernelGGL(k_sart_resid<R>, dim3(rb), dim3(kBlock), 0, s, rowptr, col, val, n_rows, nnz, nodes, b,
                            (const double *)M, (const double *)x, r);
         hipLaunchKernelGGL(k_sart_back<R>, dim3(cb), dim3(kBlock), 0, s, (const int64_t *)colptr,
-                           (const int32_t *)crow, (const R *)cval, nodes, P->sart_cap, (const double *)r,
-                           (const double *)V, lambda, x);
+                           (const CscEnt<R> *)ent, nodes, n_rows, nnz, (const double *)r, (const double *)V, lambda,
+                           x);
     }
     HIP_TRY(hipGetLastError());
     return RTX_OK;
@@ -3581,8 +3590,7 @@ int rtx_sart(rtx_plan P, int64_t n_rows, int64_t nnz, const int64_t *w_rowptr, c
     const int64_t nodes = (int64_t)P->grid.nx * P->grid.ny;
     if (n_rows == 0 || n_iter == 0) return RTX_OK;
     if (!P->sart) {
-        const size_t bytes = sizeof(double) * (2 * P->max_pairs + nodes) + sizeof(int64_t) * (nodes + 1) +
-                             sizeof(unsigned) * nodes;
+        const size_t bytes = sizeof(double) * (2 * P->max_pairs + nodes) + sizeof(int64_t) * (nodes + 1);
         if (hipMalloc(&P->sart, bytes) != hipSuccess) {
             P->sart = nullptr;
             return fail(RTX_E_NOMEM, "SART scratch allocation failed");

@@ -1,9 +1,10 @@
 """SART (Sec. 3.1's default solver of the linearised ToF subproblem) on the HIP
 path, through the C ABI: iterates against the oracle's SART on the oracle's
 system matrix, and at full size (the 256x256 workload's own matrix, 65,280
-rows) the properties that hold at any size: exact recovery of a constant
-slowness in one iteration, linearity in the data, and a decreasing row-sum
-weighted residual."""
+rows) the oracle's iterates, run-to-run identical bits, and the properties
+that hold at any size: exact recovery of a constant slowness in one
+iteration, linearity in the data, and a decreasing row-sum weighted
+residual."""
 import numpy as np
 import pytest
 
@@ -93,6 +94,13 @@ def test_sart_full_size_properties(rtx):
     x1 = plan.sart(rp, col, val, _dev(b), n_iter=3, lam=1.0).cpu().numpy().ravel()
     x2 = plan.sart(rp, col, val, _dev(2 * b), n_iter=3, lam=1.0).cpu().numpy().ravel()
     assert np.abs(x2 - 2 * x1).max() <= 1e-12 * np.abs(x1).max()
+    # (b') the same three iterations by the oracle on the same matrix; and a
+    # second call gives the same bits (the transpose keeps rows ascending inside
+    # a column, so no sum depends on the run)
+    want = oracle.sart(rpn, coln, valn, b, np.zeros(cfg["nx"] * cfg["ny"]), 3, 1.0)
+    assert np.abs(x1 - want).max() <= 1e-12 * np.abs(want).max()
+    x1b = plan.sart(rp, col, val, _dev(b), n_iter=3, lam=1.0).cpu().numpy().ravel()
+    assert np.array_equal(x1, x1b)
     # (c) the row-sum weighted residual of a consistent system decreases
     import scipy.sparse as sp
 
