@@ -97,8 +97,10 @@ def run_gpu(prec, c_host, cfg, steps, warmup, resid_host, fan=True):
 
 
 def run_sart(c_host, cfg, iters=10):
-    """SART (Sec. 3.1) on the workload's own FP32 system matrix: the once-per-
-    call setup (sums and the device transpose of W) and the time of one
+    """The path weights W of the workload's linked rays (CSR with merged rows,
+    wall time of the call that emits them), and SART (Sec. 3.1) on that FP32
+    system matrix: the once-per-call setup (sums and the device transpose of
+    W) and the time of one
     iteration (residual pass over the rows, back-projection pass over the
     columns), with its HBM rate against the algorithmic bytes of an iteration."""
     import torch
@@ -110,6 +112,15 @@ def run_sart(c_host, cfg, iters=10):
                     integ=cfg["integ"], ds_px=cfg["ds_px"], tol_px=cfg["tol_px"], max_marches=cfg["max_marches"])
     out = plan.trace(torch.from_numpy(c_host).to(dev), weights=True, fan=False)
     rp, col, val = out["w_rowptr"], out["w_col"], out["w_val"]
+
+    def timed_weights():  # the path weights W of all linked rays at their angles (CSR, merged rows)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.weights(out["theta"])
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3
+
+    w_ms = min(timed_weights() for _ in range(3))
     n_rows, nnz, nodes = rp.shape[0] - 1, col.shape[0], cfg["nx"] * cfg["ny"]
     b = torch.from_numpy(np.random.default_rng(5).standard_normal(n_rows) * 1e-6).to(dev)
     x = torch.zeros(cfg["ny"], cfg["nx"], dtype=torch.float64, device=dev)
@@ -133,7 +144,8 @@ def run_sart(c_host, cfg, iters=10):
     # rowptr/b/M/r per row, colptr/V/x per node
     bytes_it = 2 * nnz * 8 + n_rows * 32 + nodes * 32
     ms = per * iters
-    return {"rows": int(n_rows), "nnz": int(nnz), "iterations": iters, "setup_ms": setup, "ms_per_iteration": ms / iters,
+    return {"rows": int(n_rows), "nnz": int(nnz), "weights_ms": w_ms, "iterations": iters, "setup_ms": setup,
+            "ms_per_iteration": ms / iters,
             "bytes_per_iteration": int(bytes_it), "achieved_GBs": bytes_it / (ms / iters * 1e-3) / 1e9,
             "vs_hbm_peak_frac": bytes_it / (ms / iters * 1e-3) / 1e9 / PEAK_HBM_GBS}
 
@@ -294,8 +306,9 @@ def main():
                   f"{r['rays_per_s'] / 1e6:.2f} M rays/s, {r['mean_marches']:.2f} rays/pair (max {r['max_marches']})",
                   file=sys.stderr, flush=True)
     if sart:
-        print(f"# SART: setup {sart['setup_ms']:.3f} ms, {sart['ms_per_iteration']:.3f} ms/iteration on "
-              f"{sart['nnz']} entries ({sart['achieved_GBs']:.0f} GB/s)", file=sys.stderr, flush=True)
+        print(f"# path weights W: {sart['weights_ms']:.3f} ms for {sart['rows']} rows, {sart['nnz']} entries; "
+              f"SART: setup {sart['setup_ms']:.3f} ms, {sart['ms_per_iteration']:.3f} ms/iteration "
+              f"({sart['achieved_GBs']:.0f} GB/s)", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(c, cfg, resid)
     line = {
         "metric": "linked rays/s (ToF+path) and adjoint time; FP32-comp vs FP64 plain, same GPU",

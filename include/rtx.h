@@ -164,8 +164,12 @@ int rtx_set_medium(rtx_plan plan, const double *c, void *stream);
    w_col == NULL only w_rowptr [n+1] is written (count pass); otherwise w_col
    (int32 node index iy*nx+ix, ascending, unique per row) and w_val (float or
    double per precision, metres) are filled for nnz <= nnz_cap, else
-   RTX_E_CAPACITY.  Rows of pairs whose status is NO_HIT or BAD_INPUT are
-   empty.  The weights pass synchronises `stream` before returning. */
+   RTX_E_CAPACITY, with w_rowptr written all the same (so a caller can size
+   the buffers from it and call again).  Rows of pairs whose status is NO_HIT
+   or BAD_INPUT are empty.  The weights pass synchronises `stream` before
+   returning; its scratch (4 n + 1 int64, and the row entries before they are
+   merged, as int32 + value) is plan-owned and grown when a larger W
+   arrives. */
 int rtx_trace_rays(rtx_plan plan, const double *c, const int32_t *pairs, int64_t n_pairs, double *theta,
                    double *tof, double *len, double *miss_px, int32_t *n_marches, int8_t *status,
                    int64_t *w_rowptr, int32_t *w_col, void *w_val, int64_t nnz_cap, void *stream);

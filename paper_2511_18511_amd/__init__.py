@@ -47,6 +47,7 @@ class Plan:
                  max_marches=30, max_steps=0, max_pairs=None, interp="bilinear"):
         self.nx, self.ny, self.h = int(nx), int(ny), float(h)
         self.n_elem, self.radius, self.phi0 = int(n_elem), float(radius), float(phi0)
+        self._w_hint = {}  # rows -> entries to allocate first in weights()
         self.prec = prec
         self.interp = interp
         self._interp_flag = INTERPOLATIONS[interp]
@@ -181,13 +182,28 @@ class Plan:
         st = torch.empty(n, dtype=torch.int8, device=dev)
         rowptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
         self._apply(B.RTX_FIXED_ANGLE, **over)
-        B.rtx_trace_rays(self._handle, None, _ptr(pairs), n, _ptr(th), None, None, None, None, _ptr(st),
-                         _ptr(rowptr), None, None, 0, _stream())
-        nnz = int(rowptr[-1].item())
-        col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
-        val = torch.empty(max(nnz, 1), dtype=self.real, device=dev)
-        B.rtx_trace_rays(self._handle, None, _ptr(pairs), n, _ptr(th), None, None, None, None, _ptr(st),
-                         _ptr(rowptr), _ptr(col), _ptr(val), nnz, _stream())
+        # One call when the entries fit a first guess: the previous call's
+        # count plus 10 %, else ~2.5 entries per pixel of a path as long as the
+        # ring's diameter, with 50 % slack.  A call that does not fit leaves the
+        # exact row pointers in rowptr, and a second call fills exact buffers.
+        cap = self._w_hint.get(n) or n * (int(3.75 * 2 * self.radius / self.h) + 8)
+        col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        val = torch.empty(max(cap, 1), dtype=self.real, device=dev)
+        try:
+            B.rtx_trace_rays(self._handle, None, _ptr(pairs), n, _ptr(th), None, None, None, None, _ptr(st),
+                             _ptr(rowptr), _ptr(col), _ptr(val), cap, _stream())
+            nnz = int(rowptr[-1].item())
+        except B.RtxError as e:
+            if e.code != B.RTX_E_CAPACITY:
+                raise
+            nnz = int(rowptr[-1].item())
+            col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+            val = torch.empty(max(nnz, 1), dtype=self.real, device=dev)
+            B.rtx_trace_rays(self._handle, None, _ptr(pairs), n, _ptr(th), None, None, None, None, _ptr(st),
+                             _ptr(rowptr), _ptr(col), _ptr(val), nnz, _stream())
+        self._w_hint[n] = int(1.1 * nnz) + n
+        if col.shape[0] > 1.25 * nnz + 4096:  # give the slack back
+            return rowptr, col[:nnz].clone(), val[:nnz].clone()
         return rowptr, col[:nnz], val[:nnz]
 
     def adjoint(self, theta, status, resid, weight="length", c=None, pairs=None, tof=None, freqs_hz=None,

@@ -2167,27 +2167,56 @@ struct RowSink {
         }
         at++;
     }
+    __device__ __forceinline__ void emit(int32_t c, R v)
+    {
+        if (FILL) put(c, v);
+        count++;
+    }
+    // writes the sums of the cell's four corners (the end of a row)
     __device__ __forceinline__ void flush()
     {
         if (n0 >= 0) {
-            if (FILL) {
-                put(n0, a00);
-                put(n0 + 1, a10);
-                put(n0 + nx, a01);
-                put(n0 + nx + 1, a11);
-            }
-            count += 4;
+            emit(n0, a00);
+            emit(n0 + 1, a10);
+            emit(n0 + nx, a01);
+            emit(n0 + nx + 1, a11);
         }
         n0 = -1;
         a00 = a10 = a01 = a11 = (R)0;
     }
+    // the ray moves on to cell c: the two corners that c shares with the cell
+    // when they are edge neighbours carry their sums over, the others are
+    // written (a row then holds about two entries per cell instead of four)
+    __device__ __forceinline__ void move_to(int32_t c)
+    {
+        R b00 = (R)0, b10 = (R)0, b01 = (R)0, b11 = (R)0;
+        if (n0 < 0) {
+        } else if (c == n0 + 1) {
+            emit(n0, a00);
+            emit(n0 + nx, a01);
+            b00 = a10, b01 = a11;
+        } else if (c == n0 - 1) {
+            emit(n0 + 1, a10);
+            emit(n0 + nx + 1, a11);
+            b10 = a00, b11 = a01;
+        } else if (c == n0 + nx) {
+            emit(n0, a00);
+            emit(n0 + 1, a10);
+            b00 = a01, b10 = a11;
+        } else if (c == n0 - nx) {
+            emit(n0 + nx, a01);
+            emit(n0 + nx + 1, a11);
+            b01 = a00, b11 = a10;
+        } else {
+            flush();
+        }
+        n0 = c;
+        a00 = b00, a10 = b10, a01 = b01, a11 = b11;
+    }
     __device__ __forceinline__ void add(const Sample<R> &s, R a)
     {
         int32_t c = s.iy * nx + s.ix;
-        if (c != n0) {
-            flush();
-            n0 = c;
-        }
+        if (c != n0) move_to(c);
         R omt = (R)1 - s.t, oms = (R)1 - s.s;
         a00 = fma(a * omt, oms, a00);
         a10 = fma(a * s.t, oms, a10);
@@ -2300,18 +2329,18 @@ __global__ void __launch_bounds__(kBlock) k_wmerge(const int64_t *__restrict__ r
     __syncthreads();
     for (int k = 2; k <= np; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < np; i += blockDim.x) {
-                int q = i ^ j;
-                if (q > i) {
-                    bool up = (i & k) == 0;
-                    int32_t a = key[i], b = key[q];
-                    if ((a > b) == up) {
-                        key[i] = b;
-                        key[q] = a;
-                        R t = val[i];
-                        val[i] = val[q];
-                        val[q] = t;
-                    }
+            // every thread takes whole compare-exchange pairs (i, i + j): t's
+            // bits with a zero inserted at j's position give the lower index i
+            for (int t = tid; t < (np >> 1); t += blockDim.x) {
+                const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1)), q = i | j;
+                const bool up = (i & k) == 0;
+                const int32_t a = key[i], b = key[q];
+                if ((a > b) == up) {
+                    key[i] = b;
+                    key[q] = a;
+                    const R x = val[i];
+                    val[i] = val[q];
+                    val[q] = x;
                 }
             }
             __syncthreads();
@@ -2863,6 +2892,10 @@ struct rtx_plan_s {
     int8_t *f_st = nullptr;
     void *f_seed = nullptr;
     void *adj_cp = nullptr;  // adjoint: zeroed gradient copies (allocated on first use)
+    void *w_small = nullptr;  // path weights: per-row counts and offsets (w_small_bytes), kept between calls
+    size_t w_small_bytes = 0;
+    void *w_raw = nullptr;  // path weights: raw and merged row entries (w_raw_bytes), kept between calls
+    size_t w_raw_bytes = 0;
     // fan start: mid-path checkpoints of the linking rays (RayCkpt [max_pairs][2])
     // and per-pair heads, for the adjoint's split; gen counts changes of the
     // medium and of the path options (step, integrator, step limit)
@@ -3145,22 +3178,20 @@ int launch_adjoint(rtx_plan_s *P, const AdjArgs &A, R *grad, hipStream_t s)
 
 constexpr int kMergeCap = 8192;  // entries per row the LDS merge can sort
 
-// Device scratch of one weights call, freed on every exit path.
-struct Scratch {
-    std::vector<void *> ptrs;
-    ~Scratch()
-    {
-        for (void *q : ptrs) (void)hipFree(q);
+// Grows a plan-owned buffer to at least `bytes` (contents are not kept).
+static bool grow(void *&buf, size_t &have, size_t bytes)
+{
+    if (bytes <= have) return true;
+    if (buf) (void)hipFree(buf);
+    buf = nullptr;
+    have = 0;
+    if (hipMalloc(&buf, bytes) != hipSuccess) {
+        buf = nullptr;
+        return false;
     }
-    template <class T>
-    T *get(size_t n)
-    {
-        void *q = nullptr;
-        if (hipMalloc(&q, std::max<size_t>(1, n) * sizeof(T)) != hipSuccess) return nullptr;
-        ptrs.push_back(q);
-        return (T *)q;
-    }
-};
+    have = bytes;
+    return true;
+}
 
 template <class R, bool COMP>
 int emit_weights(rtx_plan_s *P, const TraceArgs &T, int64_t *w_rowptr, int32_t *w_col, R *w_val, int64_t nnz_cap,
@@ -3169,9 +3200,11 @@ int emit_weights(rtx_plan_s *P, const TraceArgs &T, int64_t *w_rowptr, int32_t *
     const int64_t n = T.n_pairs;
     Medium<R> M{(const R *)P->tab, P->grid.nx, P->grid.ny};
     Geo g = make_geo(P);
-    Scratch S;
-    int64_t *rawcnt = S.get<int64_t>(n), *rawoff = S.get<int64_t>(n), *ucnt = S.get<int64_t>(n);
-    if (!rawcnt || !rawoff || !ucnt) return fail(RTX_E_NOMEM, "weights scratch");
+    // plan-owned scratch: rawcnt, rawoff, ucnt [n] and the device row pointers
+    // [n + 1]; then the raw entries (columns, values)
+    if (!grow(P->w_small, P->w_small_bytes, sizeof(int64_t) * (4 * (size_t)n + 1)))
+        return fail(RTX_E_NOMEM, "weights scratch");
+    int64_t *rawcnt = (int64_t *)P->w_small, *rawoff = rawcnt + n, *ucnt = rawoff + n, *rowptr_d = ucnt + n;
     WArgs A;
     A.pairs = T.pairs;
     A.n_pairs = n;
@@ -3198,9 +3231,11 @@ int emit_weights(rtx_plan_s *P, const TraceArgs &T, int64_t *w_rowptr, int32_t *
     if (mx > kMergeCap)
         return fail(RTX_E_UNSUPPORTED, "a path-weight row has %lld raw entries, above the %d the row merge handles",
                     (long long)mx, kMergeCap);
-    int32_t *cols = S.get<int32_t>(total);
-    R *vals = S.get<R>(total);
-    if (!cols || !vals) return fail(RTX_E_NOMEM, "weights scratch (%lld entries)", (long long)total);
+    const size_t b_cols = ((size_t)std::max<int64_t>(total, 1) * sizeof(int32_t) + 255) & ~(size_t)255;
+    if (!grow(P->w_raw, P->w_raw_bytes, b_cols + (size_t)std::max<int64_t>(total, 1) * sizeof(R)))
+        return fail(RTX_E_NOMEM, "weights scratch (%lld entries)", (long long)total);
+    int32_t *cols = (int32_t *)P->w_raw;
+    R *vals = (R *)((char *)P->w_raw + b_cols);
     HIP_TRY(hipMemcpyAsync(rawoff, off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
     A.cols = cols;
     A.vals = vals;
@@ -3225,14 +3260,12 @@ int emit_weights(rtx_plan_s *P, const TraceArgs &T, int64_t *w_rowptr, int32_t *
             return fail(RTX_E_CAPACITY, "%lld path weights exceed nnz_cap %lld", (long long)rp[n],
                         (long long)nnz_cap);
         }
-        int64_t *rowptr_d = S.get<int64_t>(n + 1);
-        if (!rowptr_d) return fail(RTX_E_NOMEM, "weights scratch");
         HIP_TRY(hipMemcpyAsync(rowptr_d, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_wcompact<R>, dim3((unsigned)n), dim3(kBlock), 0, s, rawoff, rowptr_d, cols, vals,
                            w_col, w_val);
         HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipStreamSynchronize(s));  // host vectors and scratch die here
+    HIP_TRY(hipStreamSynchronize(s));  // host vectors die here
     return RTX_OK;
 }
 
@@ -3490,6 +3523,8 @@ int rtx_plan_destroy(rtx_plan P)
     if (P->rho) (void)hipFree(P->rho);
     if (P->omega) (void)hipFree(P->omega);
     if (P->adj_cp) (void)hipFree(P->adj_cp);
+    if (P->w_small) (void)hipFree(P->w_small);
+    if (P->w_raw) (void)hipFree(P->w_raw);
     if (P->ckpt) (void)hipFree(P->ckpt);
     if (P->ckpt_head) (void)hipFree(P->ckpt_head);
     delete P;

@@ -393,6 +393,14 @@ def test_path_weights_match_oracle(rtx, prec):
     # capacity error path
     plan = rtx.Plan(n, n, h, *ring, prec=prec)
     out2 = plan.trace(_dev(c))
+    # weights() at the same angles: the first-guess buffers (one call), then a
+    # first guess too small (the second call fills exact buffers): same CSR
+    for hint in (None, 10):
+        if hint:
+            plan._w_hint[len(pairs)] = hint
+        rp2, col2, val2 = plan.weights(_dev(th))
+        assert np.array_equal(_np(rp2), rp) and np.array_equal(_np(col2), col)
+        assert np.array_equal(_np(val2).astype(np.float64), val)
     with pytest.raises(rtx.RtxError):
         import ctypes as C
         from paper_2511_18511_amd import _binding as B
