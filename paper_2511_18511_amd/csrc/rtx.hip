@@ -2189,29 +2189,20 @@ struct RowSink {
     // written (a row then holds about two entries per cell instead of four)
     __device__ __forceinline__ void move_to(int32_t c)
     {
-        R b00 = (R)0, b10 = (R)0, b01 = (R)0, b11 = (R)0;
-        if (n0 < 0) {
-        } else if (c == n0 + 1) {
-            emit(n0, a00);
-            emit(n0 + nx, a01);
-            b00 = a10, b01 = a11;
-        } else if (c == n0 - 1) {
-            emit(n0 + 1, a10);
-            emit(n0 + nx + 1, a11);
-            b10 = a00, b11 = a01;
-        } else if (c == n0 + nx) {
-            emit(n0, a00);
-            emit(n0 + 1, a10);
-            b00 = a01, b10 = a11;
-        } else if (c == n0 - nx) {
-            emit(n0 + nx, a01);
-            emit(n0 + nx + 1, a11);
-            b01 = a00, b11 = a10;
-        } else {
-            flush();
+        // the four edge moves by selects, not branches: the lanes of a wave
+        // move in different directions
+        const bool px = c == n0 + 1, mx = c == n0 - 1, py = c == n0 + nx, my = c == n0 - nx;
+        if (n0 >= 0 && (px || mx || py || my)) {
+            emit(px || py ? n0 : mx ? n0 + 1 : n0 + nx, px || py ? a00 : mx ? a10 : a01);
+            emit(px ? n0 + nx : py ? n0 + 1 : n0 + nx + 1, px ? a01 : py ? a10 : a11);
+            const R b00 = px ? a10 : py ? a01 : (R)0, b10 = mx ? a00 : py ? a11 : (R)0;
+            const R b01 = px ? a11 : my ? a00 : (R)0, b11 = mx ? a01 : my ? a10 : (R)0;
+            a00 = b00, a10 = b10, a01 = b01, a11 = b11;
+            n0 = c;
+            return;
         }
+        flush();
         n0 = c;
-        a00 = b00, a10 = b10, a01 = b01, a11 = b11;
     }
     __device__ __forceinline__ void add(const Sample<R> &s, R a)
     {
