@@ -117,3 +117,38 @@ def test_sart_full_size_properties(rtx):
     print("weighted residual over iterations: " + ", ".join("%.3e" % v for v in res), flush=True)
     assert all(b2 < b1 for b1, b2 in zip(res, res[1:]))
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_sart_leaves_out_stray_entries(rtx, prec):
+    """Entries in no row (before the first row pointer and after the last) and
+    entries whose column lies outside the grid (-1, n*n, n*n + 7) take no part:
+    the result equals the one on the clean matrix, bit for bit (the transpose
+    sorts them into the last column, flagged; the grid's last node lies
+    outside the ring, so no kept entry shares that column, and the bad columns
+    come after row 5's own entries, so those keep their lanes)."""
+    n, h = 32, 1e-3
+    c = synth.gaussian_inclusions(n, n, h, seed=75, r_max=0.008)
+    ring = (12, 0.013, 0.0)
+    pairs = synth.all_pairs(12)
+    ref = oracle.trace(oracle.grid_medium(c, h), ring, pairs)
+    rp, col, val = oracle.weights_csr(c, h, ring, pairs, ref["theta"])
+    rng = np.random.default_rng(76)
+    b = rng.standard_normal(len(rp) - 1) * 1e-6
+    vr = val.astype(np.float32 if prec == "f32c" else np.float64)
+    plan = rtx.Plan(n, n, h, *ring, prec=prec, max_pairs=len(b))
+    x_clean = _dev(np.zeros((n, n)))
+    plan.sart(_dev(rp), _dev(col), _dev(vr), _dev(b), x=x_clean, n_iter=4, lam=1.0)
+    assert n * n - 1 not in set(col.tolist())
+    # three stray entries at the end of row 5 (bad columns), two before row 0, three after the last row
+    bad = np.array([-1, n * n, n * n + 7], np.int32)
+    k5 = rp[6]
+    col2 = np.concatenate([[3, 4], col[:k5], bad, col[k5:], [1, 2, 3]]).astype(np.int32)
+    val2 = np.concatenate([[1.0, 2.0], vr[:k5], [5.0, 6.0, 7.0], vr[k5:], [1.0, 1.0, 1.0]]).astype(vr.dtype)
+    rp2 = rp + 2
+    rp2[6:] += 3
+    x_stray = _dev(np.zeros((n, n)))
+    plan.sart(_dev(rp2), _dev(col2), _dev(val2), _dev(b), x=x_stray, n_iter=4, lam=1.0)
+    plan.close()
+    assert np.abs(x_clean.cpu().numpy()).max() > 0
+    assert np.array_equal(x_clean.cpu().numpy(), x_stray.cpu().numpy())
